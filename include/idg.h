@@ -1,0 +1,234 @@
+/*
+ * idg.h -- C ABI of an MI355X (gfx950) implementation of Image Domain Gridding
+ * (van der Tol, Veenboer & Offringa, "Image Domain Gridding: a fast method for
+ * convolutional resampling of visibilities", A&A 2018).
+ *
+ * The library partitions visibilities into subgrids (§3.2), grids each subgrid
+ * by a direct image-domain sum with per-pixel A-terms and taper (§3.3 eq.
+ * ShiftedDirectImaging, Algorithm 1, §3.5), transforms it to the uv domain and
+ * adds it to the master grid; degridding runs the adjoint chain (Algorithm 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - complex numbers are idg_cf32 {re, im} (complex64);
+ *  - master grid: grid[4][N][N] complex64, index [pol][y][x], x <-> u, y <-> v;
+ *    grid pixel x sits at u = (x - N/2) / S wavelengths (uv cell 1/S);
+ *  - visibilities: vis[nr_baselines][nr_timesteps][nr_channels][4] complex64,
+ *    polarisations XX, XY, YX, YY, i.e. the 2x2 matrix [[XX, XY], [YX, YY]];
+ *  - uvw[nr_baselines][nr_timesteps][3] float64 metres, freqs[nr_channels]
+ *    float64 Hz; a sample's uvw in wavelengths is uvw * f / c0 (§2);
+ *  - baselines[nr_baselines][2] int32 station pair (s1, s2);
+ *  - A-terms: aterms[nr_slots][nr_stations][L][L][4] complex64, a 2x2 Jones
+ *    matrix [J00, J01, J10, J11] per (slot, station, subgrid pixel [row m][col l]);
+ *    slot = timestep / aterm_timesteps, nr_slots = ceil(nr_timesteps / aterm_timesteps);
+ *  - taper: taper[L][L] float32 (the image-domain window c[i,j] of §4.2);
+ *  - subgrid image pixel (j, i) is at l = (i - L/2) S / L, m = (j - L/2) S / L,
+ *    n' = sqrt(1 - l^2 - m^2) - 1 (§2 pixel positions, §3.3);
+ *  - gridding applies c * A_s1^H Y A_s2 per pixel, degridding c * A_s1 B A_s2^H
+ *    (the polarised form of §3.5: the scalar kernel c * g_s1^* g_s2 of Algorithm 1
+ *    becomes a product of Jones matrices);
+ *  - subgrid transform: the centred DFT
+ *      V[b][a] = sum_{j,i} I[j][i] exp(-2 pi i ((a-L/2)(i-L/2) + (b-L/2)(j-L/2)) / L),
+ *    unnormalised (Algorithm 1 "FFT"); degridding uses its conjugate transpose,
+ *    also unnormalised (Algorithm 2 "IFFT"), so idg_degrid is the exact adjoint
+ *    of idg_grid on the planned samples.
+ *
+ * Pointers ending in _d are device pointers (HIP device memory of the current
+ * device); the others are host pointers.  The caller owns every data buffer;
+ * device buffers must stay valid until the work queued on `stream` has
+ * finished.  `stream` is a hipStream_t (NULL = the default stream).  Every
+ * function returns IDG_OK (0) or a negative IDG_E* code; arguments are
+ * validated before anything is queued, so nothing is written on a validation
+ * error.  No C++ exception crosses this interface.  Errors raised by queued
+ * device work surface on a later call or through idg_sync().  idg_last_error()
+ * describes the last failure of the calling thread.
+ */
+#ifndef IDG_H
+#define IDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  float re, im;
+} idg_cf32;
+
+typedef struct idg_plan_s *idg_plan_t; /* opaque; owned by the library */
+
+enum {
+  IDG_OK = 0,
+  IDG_EINVAL = -1, /* invalid argument or inconsistent sizes */
+  IDG_ENOMEM = -2, /* host or device allocation failed */
+  IDG_EHIP = -3,   /* HIP runtime or launch error */
+  IDG_ERANGE = -4, /* IDG_STRICT is set and some unflagged samples would be dropped */
+  IDG_ESTATE = -5  /* call not valid in the current state */
+};
+
+/* idg_params.flags */
+#define IDG_STRICT (1u << 0)     /* idg_plan fails with IDG_ERANGE instead of dropping samples */
+#define IDG_PHASE_FP32 (1u << 1) /* subgrid phase offsets in float32 instead of float64 (precision study) */
+
+/* Supported subgrid sizes L. */
+#define IDG_SUBGRID_SIZES {8, 16, 24, 32, 48, 64}
+
+typedef struct {
+  int32_t grid_size;       /* N: even, L <= N <= 65536 */
+  int32_t subgrid_size;    /* L: one of IDG_SUBGRID_SIZES */
+  int32_t kernel_size;     /* beta: taper support in uv pixels, 0 <= beta < L */
+  int32_t max_timesteps;   /* T_max: timesteps per subgrid, 1 .. 65535 */
+  int32_t aterm_timesteps; /* A-term slot length in timesteps, >= 1 (blocks never cross a slot) */
+  int32_t nr_stations;     /* >= 2 */
+  int32_t nr_baselines;    /* >= 0 */
+  int32_t nr_timesteps;    /* >= 0 */
+  int32_t nr_channels;     /* 0 .. 65535 */
+  uint32_t flags;          /* IDG_STRICT | IDG_PHASE_FP32 */
+  double image_size;       /* S = N * cell, direction-cosine units (> 0) */
+  int64_t scratch_bytes;   /* device budget for transformed subgrids during idg_grid; 0 = 2 GiB */
+} idg_params;
+
+/*
+ * Partition the visibilities into subgrids (§3.2 Partitioning, Fig. 2; blocks
+ * cut at A-term slot boundaries as in §3.5 Variations).  Host only: nothing is
+ * queued on a device (device metadata is uploaded on first use).
+ *
+ * Each block holds one baseline, a run of at most T_max timesteps inside one
+ * A-term slot, and a contiguous channel group, chosen so that every sample's
+ * support (the taper's beta pixels plus ceil(|w| S^2) pixels of w-support)
+ * fits the L x L box; its centre lies on the grid lattice.  Rule, in float64
+ * without contraction: x = (uvw_u * (f / c0)) * S + N/2 (same for y); a set
+ * fits iff (max x - min x) + beta + max ceil((|w| * S) * S) <= L - 1 in both
+ * axes; channel groups are split in halves while a group fails at some single
+ * timestep; time is scanned greedily; corner x0 = floor((min x + max x) * 0.5
+ * + 0.5) - L/2; a block whose box leaves [0, N) is dropped (no wrap-around), as
+ * are samples that do not fit alone.  Subgrids are ordered by baseline,
+ * channel group, time.
+ *
+ *   params     sizes and options (copied)
+ *   baselines  host int32 [nr_baselines][2], stations in [0, nr_stations), s1 != s2
+ *   uvw        host float64 [nr_baselines][nr_timesteps][3], finite
+ *   freqs      host float64 [nr_channels], finite and > 0
+ *   flags      host uint8 [nr_baselines][nr_timesteps][nr_channels], nonzero =
+ *              flagged (not gridded, written as 0 by idg_degrid); NULL = none
+ *   out        receives the plan; free it with idg_plan_destroy
+ * Errors: IDG_EINVAL (bad sizes or values), IDG_ENOMEM, IDG_ERANGE (IDG_STRICT
+ * and some unflagged sample would be dropped).  The arrays are not retained.
+ */
+int idg_plan(const idg_params *params, const int32_t *baselines, const double *uvw, const double *freqs,
+             const uint8_t *flags, idg_plan_t *out);
+
+/* Plan counters; any output pointer may be NULL.  nr_gridded + nr_dropped +
+ * nr_flagged = nr_baselines * nr_timesteps * nr_channels. */
+int idg_plan_stats(idg_plan_t plan, int64_t *nr_subgrids, int64_t *nr_gridded, int64_t *nr_dropped,
+                   int64_t *nr_flagged);
+
+/* Copy the plan to host arrays (either may be NULL):
+ *   subgrids  int64 [nr_subgrids][12]: bl, t0, nt, c0, nc, x0, y0, slot, s1, s2, nvis, vis_offset
+ *   samples   int32 [nr_gridded][2]: (timestep, channel) of each planned sample,
+ *             grouped by subgrid (rows vis_offset .. vis_offset + nvis - 1), t-major. */
+int idg_plan_export(idg_plan_t plan, int64_t *subgrids, int32_t *samples);
+
+/* Release the plan and its device metadata.  Work queued with it must have
+ * finished.  NULL is ignored. */
+void idg_plan_destroy(idg_plan_t plan);
+
+/*
+ * Image-domain gridding (Algorithm 1 without its last line, §3.3, §3.5): for
+ * every subgrid, the direct sum over its samples of Y_k exp(+2 pi i (du_k l +
+ * dv_k m + w_k n')) with du_k = u_k - u_0p computed in float64 and the
+ * per-pixel phase in float32; then c * A_s1^H S A_s2 per pixel; the centred
+ * DFT; and the sum into grid_d at corner (x0, y0).  grid_d is ACCUMULATED
+ * into (the caller zeroes it).  Results are deterministic: for each grid tile
+ * the subgrids are added in plan order.  uvw_d and freqs_d must hold the
+ * values given to idg_plan.  Device scratch of at most params.scratch_bytes is
+ * allocated stream-ordered for the call.
+ *
+ *   uvw_d    float64 [nr_baselines][nr_timesteps][3]     freqs_d  float64 [nr_channels]
+ *   vis_d    complex64 [nr_baselines][nr_timesteps][nr_channels][4]
+ *   aterms_d complex64 [nr_slots][nr_stations][L][L][4]  taper_d  float32 [L][L]
+ *   grid_d   complex64 [4][N][N], read and written
+ * Errors: IDG_EINVAL (NULL pointer), IDG_ENOMEM, IDG_EHIP.
+ */
+int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
+             const idg_cf32 *aterms_d, const float *taper_d, idg_cf32 *grid_d, void *stream);
+
+/*
+ * Image-domain degridding (Algorithm 2 after its first two lines): for every
+ * subgrid, split it out of grid_d, apply the unnormalised inverse centred DFT,
+ * apply c * A_s1 I A_s2^H per pixel, and for every sample compute
+ * sum_pix B exp(-2 pi i (du_k l + dv_k m + w_k n')).  vis_d is OVERWRITTEN:
+ * planned samples get their prediction, flagged and dropped samples get 0.
+ * Arguments as idg_grid, grid_d read only, vis_d written.
+ * Errors: IDG_EINVAL, IDG_ENOMEM, IDG_EHIP.
+ */
+int idg_degrid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *grid_d,
+               const idg_cf32 *aterms_d, const float *taper_d, idg_cf32 *vis_d, void *stream);
+
+/*
+ * Stage access for testing and measurement: run the gridder on subgrids
+ * first .. first + count - 1 of the plan and write each subgrid to
+ * out_d[count][4][L][L] complex64 ([pol][row m / v][col l / u]), either as the
+ * image after A-terms and taper (stage 0, before the transform) or as the uv
+ * subgrid after the centred DFT (stage 1).  Nothing is added to a grid.
+ * Errors: IDG_EINVAL (range or stage), IDG_EHIP.
+ */
+int idg_grid_subgrids(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
+                      const idg_cf32 *aterms_d, const float *taper_d, int64_t first, int64_t count, int32_t stage,
+                      idg_cf32 *out_d, void *stream);
+
+/*
+ * Batched centred subgrid DFT (Algorithm 1 "FFT", Algorithm 2 "IFFT") on
+ * data_d[count][4][L][L] complex64, in place, unnormalised; direction -1 is
+ * the forward transform (exp(-...)), +1 its conjugate transpose.
+ * Errors: IDG_EINVAL (L not supported, direction, count < 0), IDG_EHIP.
+ */
+int idg_subgrid_fft(idg_cf32 *data_d, int64_t count, int32_t subgrid_size, int32_t direction, void *stream);
+
+/*
+ * Adder (Algorithm 1, add subgrid to master grid): grid_d[pol][y0+b][x0+a] +=
+ * subgrids_d[s][pol][b][a] for s in 0 .. count-1 taken as plan subgrids
+ * first .. first + count - 1.  Tile ownership, deterministic order.
+ * Errors: IDG_EINVAL, IDG_ENOMEM, IDG_EHIP.
+ */
+int idg_add_subgrids(idg_plan_t plan, const idg_cf32 *subgrids_d, int64_t first, int64_t count, idg_cf32 *grid_d,
+                     void *stream);
+
+/*
+ * Splitter (Algorithm 2, initialise subgrid from master grid):
+ * subgrids_d[s][pol][b][a] = grid_d[pol][y0+b][x0+a] for plan subgrids
+ * first .. first + count - 1.
+ * Errors: IDG_EINVAL, IDG_EHIP.
+ */
+int idg_split_subgrids(idg_plan_t plan, const idg_cf32 *grid_d, int64_t first, int64_t count, idg_cf32 *subgrids_d,
+                       void *stream);
+
+/* Stage timing (the library's own tracing).  While enabled, idg_grid and
+ * idg_degrid record a pair of HIP events on their stream around every kernel
+ * they queue.  idg_profile_read waits for the recorded events and returns the
+ * accumulated milliseconds and launch counts per stage (arrays of
+ * IDG_NR_STAGES, either may be NULL), then clears them if `reset` is nonzero.
+ * Timing adds two event records per launch; it is off by default. */
+#define IDG_STAGE_GRIDDER 0
+#define IDG_STAGE_ADDER 1
+#define IDG_STAGE_DEGRIDDER 2
+#define IDG_STAGE_ZERO 3
+#define IDG_NR_STAGES 4
+int idg_profile(int enable);
+int idg_profile_read(double *ms, int64_t *launches, int reset);
+
+/* Wait for `stream` and report any error its queued work raised. */
+int idg_sync(void *stream);
+
+/* Message describing the last failure of the calling thread ("" if none). */
+const char *idg_last_error(void);
+
+/* Interface version (major * 10000 + minor * 100 + patch). */
+int idg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IDG_H */

@@ -1,0 +1,27 @@
+"""Image Domain Gridding on MI355X (gfx950): HIP kernels behind a C ABI.
+
+The hot path -- subgrid planning, the per-subgrid image-domain phasor sum with
+A-terms and taper, the subgrid transform, the adder, and the reverse chain --
+lives in libidg.so (C ABI in include/idg.h).  This package is its thin Python
+binding; device arrays are torch tensors, used only for memory and streams.
+"""
+
+from ._lib import (  # noqa: F401
+    IDG_PHASE_FP32,
+    IDG_STRICT,
+    IDGError,
+    LIB_PATH,
+    Plan,
+    SUBGRID_FIELDS,
+    add_subgrids,
+    degrid,
+    grid,
+    grid_subgrids,
+    lib,
+    profile,
+    profile_read,
+    split_subgrids,
+    subgrid_fft,
+    sync,
+    version,
+)

@@ -1,0 +1,273 @@
+"""ctypes binding of libidg.so (include/idg.h).  Argument marshalling only.
+
+Device arrays are torch tensors on a HIP device; every step of gridding and
+degridding runs in the library's kernels.  There is no fallback: if the
+library has not been built, loading it raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libidg.so")
+
+IDG_OK, IDG_EINVAL, IDG_ENOMEM, IDG_EHIP, IDG_ERANGE, IDG_ESTATE = 0, -1, -2, -3, -4, -5
+IDG_STRICT = 1 << 0
+IDG_PHASE_FP32 = 1 << 1
+
+SUBGRID_FIELDS = ("bl", "t0", "nt", "c0", "nc", "x0", "y0", "slot", "s1", "s2", "nvis", "vis_offset")
+
+EXPORTED = ("idg_plan", "idg_plan_stats", "idg_plan_export", "idg_plan_destroy", "idg_grid", "idg_degrid",
+            "idg_grid_subgrids", "idg_subgrid_fft", "idg_add_subgrids", "idg_split_subgrids", "idg_sync",
+            "idg_last_error", "idg_version", "idg_profile", "idg_profile_read")
+STAGES = ("gridder", "adder", "degridder", "zero")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("grid_size", ctypes.c_int32), ("subgrid_size", ctypes.c_int32), ("kernel_size", ctypes.c_int32),
+                ("max_timesteps", ctypes.c_int32), ("aterm_timesteps", ctypes.c_int32),
+                ("nr_stations", ctypes.c_int32), ("nr_baselines", ctypes.c_int32), ("nr_timesteps", ctypes.c_int32),
+                ("nr_channels", ctypes.c_int32), ("flags", ctypes.c_uint32), ("image_size", ctypes.c_double),
+                ("scratch_bytes", ctypes.c_int64)]
+
+
+class IDGError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"{message} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (loads it on first use)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1909_07226_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        L.idg_plan.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.idg_plan_stats.argtypes = [vp, vp, vp, vp, vp]
+        L.idg_plan_export.argtypes = [vp, vp, vp]
+        L.idg_plan_destroy.argtypes = [vp]
+        L.idg_plan_destroy.restype = None
+        L.idg_grid.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.idg_degrid.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.idg_grid_subgrids.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, i32, vp, vp]
+        L.idg_subgrid_fft.argtypes = [vp, i64, i32, i32, vp]
+        L.idg_add_subgrids.argtypes = [vp, vp, i64, i64, vp, vp]
+        L.idg_split_subgrids.argtypes = [vp, vp, i64, i64, vp, vp]
+        L.idg_sync.argtypes = [vp]
+        L.idg_last_error.restype = ctypes.c_char_p
+        L.idg_last_error.argtypes = []
+        L.idg_version.argtypes = []
+        L.idg_profile.argtypes = [ctypes.c_int]
+        L.idg_profile_read.argtypes = [vp, vp, ctypes.c_int]
+        for name in EXPORTED:
+            if name not in ("idg_plan_destroy", "idg_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        del u32
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != IDG_OK:
+        raise IDGError(rc, lib().idg_last_error().decode(errors="replace"))
+    return rc
+
+
+def _host_ptr(a, dtype, shape=None, name="array"):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    if shape is not None and arr.shape != tuple(shape):
+        raise ValueError(f"{name}: shape {arr.shape}, expected {tuple(shape)}")
+    return arr, arr.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev_ptr(t, dtype, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor on a HIP device")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: must be on a HIP device, got {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Plan:
+    """A subgrid plan (idg_plan).  Host arrays in, opaque handle kept."""
+
+    def __init__(self, grid_size, image_size, subgrid_size, kernel_size, max_timesteps, aterm_timesteps,
+                 nr_stations, baselines, uvw, freqs, flags=None, strict=False, phase_fp32=False, scratch_bytes=0):
+        uvw = np.asarray(uvw)
+        nbl, nt = uvw.shape[0], uvw.shape[1]
+        nch = int(np.asarray(freqs).size)
+        self.params = Params(int(grid_size), int(subgrid_size), int(kernel_size), int(max_timesteps),
+                             int(aterm_timesteps), int(nr_stations), nbl, nt, nch,
+                             (IDG_STRICT if strict else 0) | (IDG_PHASE_FP32 if phase_fp32 else 0),
+                             float(image_size), int(scratch_bytes))
+        self._keep = []
+        bl, blp = _host_ptr(baselines, np.int32, (nbl, 2), "baselines")
+        uv, uvp = _host_ptr(uvw, np.float64, (nbl, nt, 3), "uvw")
+        fr, frp = _host_ptr(freqs, np.float64, (nch,), "freqs")
+        fl, flp = _host_ptr(flags, np.uint8, (nbl, nt, nch), "flags")
+        h = ctypes.c_void_p()
+        self._handle = None
+        check(lib().idg_plan(ctypes.byref(self.params), blp, uvp, frp, flp, ctypes.byref(h)))
+        self._handle = h
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        return cls(wl.grid_size, wl.image_size, wl.subgrid_size, wl.kernel_size, wl.max_timesteps,
+                   wl.aterm_timesteps, wl.nr_stations, wl.baselines, wl.uvw, wl.freqs, wl.flags, **kw)
+
+    def __del__(self):
+        if getattr(self, "_handle", None) is not None and _lib is not None:
+            _lib.idg_plan_destroy(self._handle)
+            self._handle = None
+
+    @property
+    def handle(self):
+        return self._handle
+
+    @property
+    def grid_size(self):
+        return self.params.grid_size
+
+    @property
+    def subgrid_size(self):
+        return self.params.subgrid_size
+
+    def stats(self):
+        v = [ctypes.c_int64() for _ in range(4)]
+        check(lib().idg_plan_stats(self._handle, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("nr_subgrids", "nr_gridded", "nr_dropped", "nr_flagged"), (x.value for x in v)))
+
+    @property
+    def nr_subgrids(self):
+        return self.stats()["nr_subgrids"]
+
+    def export(self):
+        """(subgrids int64 [P, 12] with SUBGRID_FIELDS columns, samples int32 [K, 2] of (t, c))."""
+        st = self.stats()
+        sub = np.zeros((st["nr_subgrids"], 12), np.int64)
+        smp = np.zeros((st["nr_gridded"], 2), np.int32)
+        check(lib().idg_plan_export(self._handle, sub.ctypes.data_as(ctypes.c_void_p),
+                                    smp.ctypes.data_as(ctypes.c_void_p)))
+        return sub, smp
+
+    # shapes of the device arrays
+    def shapes(self, nr_slots=None):
+        p = self.params
+        L, N = p.subgrid_size, p.grid_size
+        ns = -(-p.nr_timesteps // p.aterm_timesteps) if nr_slots is None else nr_slots
+        return dict(uvw=(p.nr_baselines, p.nr_timesteps, 3), freqs=(p.nr_channels,),
+                    vis=(p.nr_baselines, p.nr_timesteps, p.nr_channels, 4), aterms=(ns, p.nr_stations, L, L, 4),
+                    taper=(L, L), grid=(4, N, N))
+
+
+def _common(plan, uvw_d, freqs_d, aterms_d, taper_d):
+    import torch
+    sh = plan.shapes()
+    return (_dev_ptr(uvw_d, torch.float64, sh["uvw"], "uvw"), _dev_ptr(freqs_d, torch.float64, sh["freqs"], "freqs"),
+            _dev_ptr(aterms_d, torch.complex64, sh["aterms"], "aterms"),
+            _dev_ptr(taper_d, torch.float32, sh["taper"], "taper"))
+
+
+def grid(plan, uvw_d, freqs_d, vis_d, aterms_d, taper_d, grid_d, stream=None):
+    """idg_grid: accumulate the plan's visibilities into grid_d [4, N, N] complex64."""
+    import torch
+    sh = plan.shapes()
+    u, f, a, t = _common(plan, uvw_d, freqs_d, aterms_d, taper_d)
+    check(lib().idg_grid(plan.handle, u, f, _dev_ptr(vis_d, torch.complex64, sh["vis"], "vis"), a, t,
+                         _dev_ptr(grid_d, torch.complex64, sh["grid"], "grid"), _stream_ptr(stream)))
+
+
+def degrid(plan, uvw_d, freqs_d, grid_d, aterms_d, taper_d, vis_d, stream=None):
+    """idg_degrid: overwrite vis_d [nbl, nt, nch, 4] complex64 with predictions from grid_d."""
+    import torch
+    sh = plan.shapes()
+    u, f, a, t = _common(plan, uvw_d, freqs_d, aterms_d, taper_d)
+    check(lib().idg_degrid(plan.handle, u, f, _dev_ptr(grid_d, torch.complex64, sh["grid"], "grid"), a, t,
+                           _dev_ptr(vis_d, torch.complex64, sh["vis"], "vis"), _stream_ptr(stream)))
+
+
+def grid_subgrids(plan, uvw_d, freqs_d, vis_d, aterms_d, taper_d, first, count, stage, out_d, stream=None):
+    """idg_grid_subgrids: subgrids [count, 4, L, L] before (stage 0) or after (stage 1) the transform."""
+    import torch
+    sh = plan.shapes()
+    L = plan.subgrid_size
+    u, f, a, t = _common(plan, uvw_d, freqs_d, aterms_d, taper_d)
+    check(lib().idg_grid_subgrids(plan.handle, u, f, _dev_ptr(vis_d, torch.complex64, sh["vis"], "vis"), a, t,
+                                  int(first), int(count), int(stage),
+                                  _dev_ptr(out_d, torch.complex64, (count, 4, L, L), "out"), _stream_ptr(stream)))
+
+
+def subgrid_fft(data_d, direction, stream=None):
+    """idg_subgrid_fft in place on data_d [count, 4, L, L] complex64; direction -1 forward, +1 inverse."""
+    import torch
+    if data_d.dim() != 4 or data_d.shape[1] != 4 or data_d.shape[2] != data_d.shape[3]:
+        raise ValueError("data: expected shape [count, 4, L, L]")
+    p = _dev_ptr(data_d, torch.complex64, None, "data")
+    check(lib().idg_subgrid_fft(p, int(data_d.shape[0]), int(data_d.shape[2]), int(direction), _stream_ptr(stream)))
+
+
+def add_subgrids(plan, subgrids_d, first, grid_d, stream=None):
+    """idg_add_subgrids: grid_d += subgrids_d [count, 4, L, L] at the corners of plan subgrids first..."""
+    import torch
+    L = plan.subgrid_size
+    count = int(subgrids_d.shape[0])
+    check(lib().idg_add_subgrids(plan.handle, _dev_ptr(subgrids_d, torch.complex64, (count, 4, L, L), "subgrids"),
+                                 int(first), count,
+                                 _dev_ptr(grid_d, torch.complex64, plan.shapes()["grid"], "grid"),
+                                 _stream_ptr(stream)))
+
+
+def split_subgrids(plan, grid_d, first, out_d, stream=None):
+    """idg_split_subgrids: out_d [count, 4, L, L] = grid_d windows of plan subgrids first..."""
+    import torch
+    L = plan.subgrid_size
+    count = int(out_d.shape[0])
+    check(lib().idg_split_subgrids(plan.handle, _dev_ptr(grid_d, torch.complex64, plan.shapes()["grid"], "grid"),
+                                   int(first), count, _dev_ptr(out_d, torch.complex64, (count, 4, L, L), "out"),
+                                   _stream_ptr(stream)))
+
+
+def sync(stream=None):
+    check(lib().idg_sync(_stream_ptr(stream)))
+
+
+def version():
+    return lib().idg_version()
+
+
+def profile(enable=True):
+    """Turn the library's per-stage HIP-event timing on or off (idg_profile)."""
+    check(lib().idg_profile(1 if enable else 0))
+
+
+def profile_read(reset=True):
+    """{stage: (milliseconds, launches)} accumulated since the last reset (idg_profile_read)."""
+    ms = np.zeros(len(STAGES), np.float64)
+    n = np.zeros(len(STAGES), np.int64)
+    check(lib().idg_profile_read(ms.ctypes.data_as(ctypes.c_void_p), n.ctypes.data_as(ctypes.c_void_p),
+                                 1 if reset else 0))
+    return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}

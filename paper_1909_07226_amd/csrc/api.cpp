@@ -1,0 +1,676 @@
+// C ABI of the image-domain gridding library: validation, plan upload, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "idg.h"
+#include "internal.h"
+#include "plan.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(IDG_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), int(e));
+}
+
+#define HIP_TRY(expr, what)                  \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr int64_t kDefaultScratch = int64_t(2) << 30;
+
+// Device-resident plan metadata on one device.
+struct Batch {
+  int64_t first = 0, count = 0;    // plan subgrids [first, first + count)
+  int64_t tile_off = 0, ntiles = 0;  // rows in tile_ids; tile_start rows tile_off + b .. (ntiles + 1 entries)
+  int64_t start_off = 0;
+};
+
+struct DevPlan {
+  int device = -1;
+  idg::DevSubgrid *subgrids = nullptr;
+  uint32_t *samples = nullptr;
+  int64_t *unplanned = nullptr;
+  float4 *lmn = nullptr;
+  float2 *twiddle = nullptr;
+  int32_t *tile_ids = nullptr, *tile_start = nullptr, *contrib = nullptr;
+  std::vector<Batch> batches;
+  int64_t batch_size = 0;
+
+  ~DevPlan() {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != device) (void)hipSetDevice(device);
+    void *ptrs[] = {subgrids, samples, unplanned, lmn, twiddle, tile_ids, tile_start, contrib};
+    for (void *p : ptrs)
+      if (p) (void)hipFree(p);
+    if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+  }
+};
+
+struct TileLists {
+  std::vector<int32_t> tile_ids, tile_start, contrib;
+};
+
+// Tile ownership for the adder: for every grid tile, the local indices of the
+// subgrids that overlap it, ascending; tiles with more work first.
+void build_tile_lists(const std::vector<idg::SubgridRec> &subs, int64_t first, int64_t count, int N, int L,
+                      TileLists &out) {
+  const int T = idg::kAdderTile;
+  const int ntx = (N + T - 1) / T;
+  const int64_t ntile = int64_t(ntx) * ntx;
+  std::vector<int32_t> cnt(size_t(ntile) + 1, 0);
+  auto each_tile = [&](const idg::SubgridRec &r, auto &&fn) {
+    for (int ty = r.y0 / T; ty <= (r.y0 + L - 1) / T; ++ty)
+      for (int tx = r.x0 / T; tx <= (r.x0 + L - 1) / T; ++tx) fn(int64_t(ty) * ntx + tx);
+  };
+  for (int64_t s = 0; s < count; ++s) each_tile(subs[size_t(first + s)], [&](int64_t t) { cnt[size_t(t)]++; });
+  std::vector<int64_t> off(size_t(ntile) + 1, 0);
+  for (int64_t t = 0; t < ntile; ++t) off[size_t(t) + 1] = off[size_t(t)] + cnt[size_t(t)];
+  std::vector<int32_t> flat(static_cast<size_t>(off[static_cast<size_t>(ntile)]));
+  std::vector<int64_t> pos(off.begin(), off.end() - 1);
+  for (int64_t s = 0; s < count; ++s)
+    each_tile(subs[size_t(first + s)], [&](int64_t t) { flat[size_t(pos[size_t(t)]++)] = int32_t(s); });
+  std::vector<int32_t> active;
+  for (int64_t t = 0; t < ntile; ++t)
+    if (cnt[size_t(t)]) active.push_back(int32_t(t));
+  std::stable_sort(active.begin(), active.end(),
+                   [&](int32_t a, int32_t b) { return cnt[size_t(a)] > cnt[size_t(b)]; });
+  out.tile_ids = active;
+  out.tile_start.resize(active.size() + 1);
+  out.contrib.clear();
+  out.contrib.reserve(flat.size());
+  out.tile_start[0] = 0;
+  for (size_t i = 0; i < active.size(); ++i) {
+    const int64_t t = active[i];
+    out.contrib.insert(out.contrib.end(), flat.begin() + off[size_t(t)], flat.begin() + off[size_t(t) + 1]);
+    out.tile_start[i + 1] = int32_t(out.contrib.size());
+  }
+}
+
+// Stage timing with HIP events on the launching stream (idg_profile).
+struct Profiler {
+  struct Rec {
+    int stage;
+    hipEvent_t start, stop;
+  };
+  std::mutex mu;
+  bool on = false;
+  std::vector<Rec> pending;
+  double ms[IDG_NR_STAGES] = {};
+  int64_t launches[IDG_NR_STAGES] = {};
+};
+
+Profiler &profiler() {
+  static Profiler p;
+  return p;
+}
+
+// Brackets one kernel launch when profiling is on.
+class StageTimer {
+ public:
+  StageTimer(int stage, hipStream_t s) : stage_(stage), s_(s) {
+    Profiler &p = profiler();
+    std::lock_guard<std::mutex> lock(p.mu);
+    if (!p.on) return;
+    if (hipEventCreate(&a_) != hipSuccess) return;
+    if (hipEventCreate(&b_) != hipSuccess) {
+      (void)hipEventDestroy(a_);
+      return;
+    }
+    active_ = hipEventRecord(a_, s_) == hipSuccess;
+  }
+  ~StageTimer() {
+    if (!active_) return;
+    Profiler &p = profiler();
+    if (hipEventRecord(b_, s_) != hipSuccess) {
+      (void)hipEventDestroy(a_);
+      (void)hipEventDestroy(b_);
+      return;
+    }
+    std::lock_guard<std::mutex> lock(p.mu);
+    p.pending.push_back({stage_, a_, b_});
+  }
+
+ private:
+  int stage_;
+  hipStream_t s_;
+  hipEvent_t a_{}, b_{};
+  bool active_ = false;
+};
+
+template <typename T>
+int upload(T **dst, const T *src, size_t n, const char *what) {
+  *dst = nullptr;
+  if (n == 0) return IDG_OK;
+  HIP_TRY(hipMalloc(reinterpret_cast<void **>(dst), n * sizeof(T)), what);
+  HIP_TRY(hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice), what);
+  return IDG_OK;
+}
+
+}  // namespace
+
+struct idg_plan_s {
+  idg::HostPlan host;
+  std::mutex mu;
+  std::map<int, std::unique_ptr<DevPlan>> dev;
+};
+
+namespace {
+
+int64_t batch_size_of(const idg_params &p) {
+  const int64_t per = int64_t(4) * p.subgrid_size * p.subgrid_size * int64_t(sizeof(idg_cf32));
+  const int64_t budget = p.scratch_bytes > 0 ? p.scratch_bytes : kDefaultScratch;
+  return std::max<int64_t>(1, std::min<int64_t>(budget / per, int64_t(1) << 30));
+}
+
+void lmn_table(int L, double S, std::vector<float4> &lmn, std::vector<float2> &tw) {
+  lmn.resize(size_t(L) * L);
+  for (int j = 0; j < L; ++j)
+    for (int i = 0; i < L; ++i) {
+      const double l = (i - L / 2) * (S / L), m = (j - L / 2) * (S / L);
+      const double r2 = l * l + m * m;
+      const double n = -r2 / (1.0 + std::sqrt(1.0 - r2));  // sqrt(1 - r2) - 1 without cancellation
+      lmn[size_t(j) * L + i] = make_float4(float(l), float(m), float(n), 0.0f);
+    }
+  tw.resize(size_t(L));
+  for (int k = 0; k < L; ++k) {
+    const double ph = -2.0 * M_PI * k / L;
+    tw[size_t(k)] = make_float2(float(std::cos(ph)), float(std::sin(ph)));
+  }
+}
+
+// Device metadata of `plan` on the current device, uploaded on first use.
+int device_plan(idg_plan_t plan, DevPlan **out) {
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+  std::lock_guard<std::mutex> lock(plan->mu);
+  auto it = plan->dev.find(device);
+  if (it != plan->dev.end()) {
+    *out = it->second.get();
+    return IDG_OK;
+  }
+  const idg::HostPlan &h = plan->host;
+  const idg_params &p = h.params;
+  auto dp = std::make_unique<DevPlan>();
+  dp->device = device;
+  const int L = p.subgrid_size;
+  std::vector<idg::DevSubgrid> subs(h.subgrids.size());
+  for (size_t i = 0; i < subs.size(); ++i) {
+    const auto &r = h.subgrids[i];
+    idg::DevSubgrid &d = subs[i];
+    d.bl = r.bl;
+    d.t0 = r.t0;
+    d.c0 = r.c0;
+    d.nvis = r.nvis;
+    d.x0 = r.x0;
+    d.y0 = r.y0;
+    d.a1 = r.slot * p.nr_stations + r.s1;
+    d.a2 = r.slot * p.nr_stations + r.s2;
+    d.vis_offset = r.vis_offset;
+    d.pad = 0;
+  }
+  std::vector<float4> lmn;
+  std::vector<float2> tw;
+  lmn_table(L, p.image_size, lmn, tw);
+  int rc;
+  if ((rc = upload(&dp->subgrids, subs.data(), subs.size(), "plan upload (subgrids)")) != IDG_OK) return rc;
+  if ((rc = upload(&dp->samples, h.samples.data(), h.samples.size(), "plan upload (samples)")) != IDG_OK) return rc;
+  if ((rc = upload(&dp->unplanned, h.unplanned.data(), h.unplanned.size(), "plan upload (unplanned)")) != IDG_OK)
+    return rc;
+  if ((rc = upload(&dp->lmn, lmn.data(), lmn.size(), "plan upload (lmn)")) != IDG_OK) return rc;
+  if ((rc = upload(&dp->twiddle, tw.data(), tw.size(), "plan upload (twiddle)")) != IDG_OK) return rc;
+
+  // adder tile lists, one set per scratch batch
+  const int64_t P = int64_t(h.subgrids.size());
+  dp->batch_size = batch_size_of(p);
+  std::vector<int32_t> all_ids, all_start, all_contrib;
+  for (int64_t f = 0; f < P; f += dp->batch_size) {
+    Batch b;
+    b.first = f;
+    b.count = std::min(dp->batch_size, P - f);
+    TileLists tl;
+    build_tile_lists(h.subgrids, b.first, b.count, p.grid_size, L, tl);
+    b.tile_off = int64_t(all_ids.size());
+    b.ntiles = int64_t(tl.tile_ids.size());
+    b.start_off = int64_t(all_start.size());
+    const int32_t base = int32_t(all_contrib.size());
+    all_ids.insert(all_ids.end(), tl.tile_ids.begin(), tl.tile_ids.end());
+    for (int32_t v : tl.tile_start) all_start.push_back(base + v);
+    all_contrib.insert(all_contrib.end(), tl.contrib.begin(), tl.contrib.end());
+    dp->batches.push_back(b);
+  }
+  if ((rc = upload(&dp->tile_ids, all_ids.data(), all_ids.size(), "plan upload (tiles)")) != IDG_OK) return rc;
+  if ((rc = upload(&dp->tile_start, all_start.data(), all_start.size(), "plan upload (tiles)")) != IDG_OK) return rc;
+  if ((rc = upload(&dp->contrib, all_contrib.data(), all_contrib.size(), "plan upload (tiles)")) != IDG_OK) return rc;
+  *out = dp.get();
+  plan->dev.emplace(device, std::move(dp));
+  return IDG_OK;
+}
+
+// Twiddle table exp(-2 pi i k / L) per (device, L) for the standalone transform; kept for the process.
+int device_twiddle(int L, const float2 **out) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, float2 *> cache;
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+  std::lock_guard<std::mutex> lock(mu);
+  auto key = std::make_pair(device, L);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    std::vector<float4> lmn;
+    std::vector<float2> tw;
+    lmn_table(L, 1.0, lmn, tw);
+    float2 *d = nullptr;
+    int rc = upload(&d, tw.data(), tw.size(), "twiddle upload");
+    if (rc != IDG_OK) return rc;
+    it = cache.emplace(key, d).first;
+  }
+  *out = it->second;
+  return IDG_OK;
+}
+
+int validate_params(const idg_params *p) {
+  if (!p) return fail(IDG_EINVAL, "idg_plan: params is NULL");
+  if (!idg::supported_subgrid_size(p->subgrid_size))
+    return fail(IDG_EINVAL, "subgrid_size %d not supported (8, 16, 24, 32, 48 or 64)", p->subgrid_size);
+  if (p->grid_size < p->subgrid_size || p->grid_size > 65536 || (p->grid_size & 1))
+    return fail(IDG_EINVAL, "grid_size %d must be even and in [subgrid_size, 65536]", p->grid_size);
+  if (p->kernel_size < 0 || p->kernel_size >= p->subgrid_size)
+    return fail(IDG_EINVAL, "kernel_size %d must be in [0, subgrid_size)", p->kernel_size);
+  if (p->max_timesteps < 1 || p->max_timesteps > 65535)
+    return fail(IDG_EINVAL, "max_timesteps %d must be in [1, 65535]", p->max_timesteps);
+  if (p->aterm_timesteps < 1) return fail(IDG_EINVAL, "aterm_timesteps must be >= 1");
+  if (p->nr_stations < 2) return fail(IDG_EINVAL, "nr_stations must be >= 2");
+  if (p->nr_baselines < 0 || p->nr_timesteps < 0 || p->nr_channels < 0 || p->nr_channels > 65535)
+    return fail(IDG_EINVAL, "negative size or nr_channels > 65535");
+  if (!(p->image_size > 0.0) || !(p->image_size <= 1.4))
+    return fail(IDG_EINVAL, "image_size must be in (0, 1.4] (direction cosines)");
+  if (p->scratch_bytes < 0) return fail(IDG_EINVAL, "scratch_bytes must be >= 0");
+  if (p->flags & ~uint32_t(IDG_STRICT | IDG_PHASE_FP32)) return fail(IDG_EINVAL, "unknown flags 0x%x", p->flags);
+  const int64_t total = int64_t(p->nr_baselines) * p->nr_timesteps * p->nr_channels;
+  if (total > (int64_t(1) << 40)) return fail(IDG_EINVAL, "too many samples");
+  return IDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int idg_version(void) { return 10000; }
+
+const char *idg_last_error(void) { return g_last_error.c_str(); }
+
+int idg_plan(const idg_params *params, const int32_t *baselines, const double *uvw, const double *freqs,
+             const uint8_t *flags, idg_plan_t *out) {
+  if (!out) return fail(IDG_EINVAL, "idg_plan: out is NULL");
+  *out = nullptr;
+  int rc = validate_params(params);
+  if (rc != IDG_OK) return rc;
+  const idg_params &p = *params;
+  const int64_t nbt = int64_t(p.nr_baselines) * p.nr_timesteps;
+  if (p.nr_baselines > 0 && !baselines) return fail(IDG_EINVAL, "idg_plan: baselines is NULL");
+  if (nbt > 0 && !uvw) return fail(IDG_EINVAL, "idg_plan: uvw is NULL");
+  if (p.nr_channels > 0 && !freqs) return fail(IDG_EINVAL, "idg_plan: freqs is NULL");
+  for (int b = 0; b < p.nr_baselines; ++b) {
+    const int s1 = baselines[2 * b], s2 = baselines[2 * b + 1];
+    if (s1 < 0 || s2 < 0 || s1 >= p.nr_stations || s2 >= p.nr_stations || s1 == s2)
+      return fail(IDG_EINVAL, "idg_plan: baseline %d has invalid stations (%d, %d)", b, s1, s2);
+  }
+  for (int64_t i = 0; i < nbt * 3; ++i)
+    if (!std::isfinite(uvw[i])) return fail(IDG_EINVAL, "idg_plan: uvw[%lld] is not finite", (long long)i);
+  for (int c = 0; c < p.nr_channels; ++c)
+    if (!std::isfinite(freqs[c]) || !(freqs[c] > 0.0))
+      return fail(IDG_EINVAL, "idg_plan: freqs[%d] must be finite and > 0", c);
+  idg_plan_s *plan = new (std::nothrow) idg_plan_s;
+  if (!plan) return fail(IDG_ENOMEM, "idg_plan: out of host memory");
+  std::string err;
+  rc = idg::build_plan(p, baselines, uvw, freqs, flags, plan->host, err);
+  if (rc != IDG_OK) {
+    delete plan;
+    return fail(rc, "%s", err.c_str());
+  }
+  if ((p.flags & IDG_STRICT) && plan->host.nr_dropped > 0) {
+    const long long nd = (long long)plan->host.nr_dropped;
+    delete plan;
+    return fail(IDG_ERANGE, "idg_plan: %lld unflagged samples do not fit a subgrid (IDG_STRICT)", nd);
+  }
+  *out = plan;
+  return IDG_OK;
+}
+
+int idg_plan_stats(idg_plan_t plan, int64_t *nr_subgrids, int64_t *nr_gridded, int64_t *nr_dropped,
+                   int64_t *nr_flagged) {
+  if (!plan) return fail(IDG_EINVAL, "idg_plan_stats: plan is NULL");
+  if (nr_subgrids) *nr_subgrids = int64_t(plan->host.subgrids.size());
+  if (nr_gridded) *nr_gridded = plan->host.nr_gridded;
+  if (nr_dropped) *nr_dropped = plan->host.nr_dropped;
+  if (nr_flagged) *nr_flagged = plan->host.nr_flagged;
+  return IDG_OK;
+}
+
+int idg_plan_export(idg_plan_t plan, int64_t *subgrids, int32_t *samples) {
+  if (!plan) return fail(IDG_EINVAL, "idg_plan_export: plan is NULL");
+  const idg::HostPlan &h = plan->host;
+  if (subgrids) {
+    for (size_t i = 0; i < h.subgrids.size(); ++i) {
+      const auto &r = h.subgrids[i];
+      int64_t *o = subgrids + i * 12;
+      o[0] = r.bl; o[1] = r.t0; o[2] = r.nt; o[3] = r.c0; o[4] = r.nc; o[5] = r.x0;
+      o[6] = r.y0; o[7] = r.slot; o[8] = r.s1; o[9] = r.s2; o[10] = r.nvis; o[11] = r.vis_offset;
+    }
+  }
+  if (samples) {
+    for (const auto &r : h.subgrids)
+      for (int64_t k = 0; k < r.nvis; ++k) {
+        const uint32_t pk = h.samples[size_t(r.vis_offset + k)];
+        samples[2 * (r.vis_offset + k)] = r.t0 + int32_t(pk >> 16);
+        samples[2 * (r.vis_offset + k) + 1] = r.c0 + int32_t(pk & 0xffffu);
+      }
+  }
+  return IDG_OK;
+}
+
+void idg_plan_destroy(idg_plan_t plan) { delete plan; }
+
+static void fill_kernel_args(const idg_plan_s *plan, const DevPlan *dp, idg::KernelArgs &a) {
+  const idg_params &p = plan->host.params;
+  a = idg::KernelArgs{};
+  a.subgrids = dp->subgrids;
+  a.samples = dp->samples;
+  a.lmn = dp->lmn;
+  a.twiddle = dp->twiddle;
+  a.nr_timesteps = p.nr_timesteps;
+  a.nr_channels = p.nr_channels;
+  a.grid_size = p.grid_size;
+  a.image_size = p.image_size;
+  a.phase_fp32 = (p.flags & IDG_PHASE_FP32) ? 1 : 0;
+}
+
+int idg_grid_subgrids(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
+                      const idg_cf32 *aterms_d, const float *taper_d, int64_t first, int64_t count, int32_t stage,
+                      idg_cf32 *out_d, void *stream) {
+  if (!plan) return fail(IDG_EINVAL, "idg_grid_subgrids: plan is NULL");
+  const int64_t P = int64_t(plan->host.subgrids.size());
+  if (first < 0 || count < 0 || first + count > P)
+    return fail(IDG_EINVAL, "idg_grid_subgrids: range [%lld, %lld) outside [0, %lld)", (long long)first,
+                (long long)(first + count), (long long)P);
+  if (stage != 0 && stage != 1) return fail(IDG_EINVAL, "idg_grid_subgrids: stage must be 0 or 1");
+  if (count == 0) return IDG_OK;
+  if (!uvw_d || !freqs_d || !vis_d || !aterms_d || !taper_d || !out_d)
+    return fail(IDG_EINVAL, "idg_grid_subgrids: NULL device pointer");
+  DevPlan *dp = nullptr;
+  int rc = device_plan(plan, &dp);
+  if (rc != IDG_OK) return rc;
+  idg::KernelArgs a;
+  fill_kernel_args(plan, dp, a);
+  a.uvw = uvw_d;
+  a.freqs = freqs_d;
+  a.vis_in = reinterpret_cast<const float2 *>(vis_d);
+  a.aterms = reinterpret_cast<const float2 *>(aterms_d);
+  a.taper = taper_d;
+  a.subgrids_out = reinterpret_cast<float2 *>(out_d);
+  a.stage = stage;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int L = plan->host.params.subgrid_size;
+  for (int64_t f = 0; f < count; f += (int64_t(1) << 30)) {
+    a.first = first + f;
+    a.count = int32_t(std::min<int64_t>(count - f, int64_t(1) << 30));
+    a.subgrids_out = reinterpret_cast<float2 *>(out_d) + f * 4 * L * L;
+    HIP_TRY(idg::launch_gridder(L, a, s), "gridder launch");
+  }
+  return IDG_OK;
+}
+
+int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
+             const idg_cf32 *aterms_d, const float *taper_d, idg_cf32 *grid_d, void *stream) {
+  if (!plan) return fail(IDG_EINVAL, "idg_grid: plan is NULL");
+  if (plan->host.subgrids.empty()) return IDG_OK;
+  if (!uvw_d || !freqs_d || !vis_d || !aterms_d || !taper_d || !grid_d)
+    return fail(IDG_EINVAL, "idg_grid: NULL device pointer");
+  DevPlan *dp = nullptr;
+  int rc = device_plan(plan, &dp);
+  if (rc != IDG_OK) return rc;
+  const idg_params &p = plan->host.params;
+  const int L = p.subgrid_size;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t per = int64_t(4) * L * L;
+  const int64_t nb = std::min<int64_t>(dp->batch_size, int64_t(plan->host.subgrids.size()));
+  float2 *scratch = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&scratch), size_t(nb * per) * sizeof(float2), s),
+          "idg_grid: scratch allocation");
+  idg::KernelArgs a;
+  fill_kernel_args(plan, dp, a);
+  a.uvw = uvw_d;
+  a.freqs = freqs_d;
+  a.vis_in = reinterpret_cast<const float2 *>(vis_d);
+  a.aterms = reinterpret_cast<const float2 *>(aterms_d);
+  a.taper = taper_d;
+  a.subgrids_out = scratch;
+  a.stage = 1;
+  hipError_t err = hipSuccess;
+  for (const Batch &b : dp->batches) {
+    a.first = b.first;
+    a.count = int32_t(b.count);
+    {
+      StageTimer tm(IDG_STAGE_GRIDDER, s);
+      err = idg::launch_gridder(L, a, s);
+    }
+    if (err != hipSuccess) break;
+    idg::AdderArgs ad;
+    ad.subgrids = dp->subgrids;
+    ad.first = b.first;
+    ad.tile_ids = dp->tile_ids + b.tile_off;
+    ad.tile_start = dp->tile_start + b.start_off;
+    ad.contrib = dp->contrib;
+    ad.subgrids_in = scratch;
+    ad.grid = reinterpret_cast<float2 *>(grid_d);
+    ad.ntiles = int32_t(b.ntiles);
+    ad.ntx = (p.grid_size + idg::kAdderTile - 1) / idg::kAdderTile;
+    ad.grid_size = p.grid_size;
+    {
+      StageTimer tm(IDG_STAGE_ADDER, s);
+      err = idg::launch_adder(L, ad, s);
+    }
+    if (err != hipSuccess) break;
+  }
+  hipError_t ef = hipFreeAsync(scratch, s);
+  if (err != hipSuccess) return hip_fail(err, "idg_grid: launch");
+  HIP_TRY(ef, "idg_grid: scratch release");
+  return IDG_OK;
+}
+
+int idg_degrid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *grid_d,
+               const idg_cf32 *aterms_d, const float *taper_d, idg_cf32 *vis_d, void *stream) {
+  if (!plan) return fail(IDG_EINVAL, "idg_degrid: plan is NULL");
+  const idg::HostPlan &h = plan->host;
+  if (h.subgrids.empty() && h.unplanned.empty()) return IDG_OK;
+  if (!uvw_d || !freqs_d || !grid_d || !aterms_d || !taper_d || !vis_d)
+    return fail(IDG_EINVAL, "idg_degrid: NULL device pointer");
+  DevPlan *dp = nullptr;
+  int rc = device_plan(plan, &dp);
+  if (rc != IDG_OK) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!h.unplanned.empty()) {
+    StageTimer tm(IDG_STAGE_ZERO, s);
+    HIP_TRY(idg::launch_zero_samples(dp->unplanned, int64_t(h.unplanned.size()), reinterpret_cast<float2 *>(vis_d), s),
+            "idg_degrid: zero launch");
+  }
+  idg::KernelArgs a;
+  fill_kernel_args(plan, dp, a);
+  a.uvw = uvw_d;
+  a.freqs = freqs_d;
+  a.grid_in = reinterpret_cast<const float2 *>(grid_d);
+  a.vis_out = reinterpret_cast<float2 *>(vis_d);
+  a.aterms = reinterpret_cast<const float2 *>(aterms_d);
+  a.taper = taper_d;
+  const int64_t P = int64_t(h.subgrids.size());
+  for (int64_t f = 0; f < P; f += (int64_t(1) << 30)) {
+    a.first = f;
+    a.count = int32_t(std::min<int64_t>(P - f, int64_t(1) << 30));
+    StageTimer tm(IDG_STAGE_DEGRIDDER, s);
+    HIP_TRY(idg::launch_degridder(h.params.subgrid_size, a, s), "idg_degrid: launch");
+  }
+  return IDG_OK;
+}
+
+int idg_subgrid_fft(idg_cf32 *data_d, int64_t count, int32_t subgrid_size, int32_t direction, void *stream) {
+  if (!idg::supported_subgrid_size(subgrid_size))
+    return fail(IDG_EINVAL, "idg_subgrid_fft: subgrid_size %d not supported", subgrid_size);
+  if (direction != -1 && direction != 1) return fail(IDG_EINVAL, "idg_subgrid_fft: direction must be -1 or +1");
+  if (count < 0 || count > (int64_t(1) << 31) - 1) return fail(IDG_EINVAL, "idg_subgrid_fft: bad count");
+  if (count == 0) return IDG_OK;
+  if (!data_d) return fail(IDG_EINVAL, "idg_subgrid_fft: data is NULL");
+  const float2 *tw = nullptr;
+  int rc = device_twiddle(subgrid_size, &tw);
+  if (rc != IDG_OK) return rc;
+  HIP_TRY(idg::launch_subgrid_fft(subgrid_size, reinterpret_cast<float2 *>(data_d), count, direction, tw,
+                                  static_cast<hipStream_t>(stream)),
+          "idg_subgrid_fft: launch");
+  return IDG_OK;
+}
+
+int idg_add_subgrids(idg_plan_t plan, const idg_cf32 *subgrids_d, int64_t first, int64_t count, idg_cf32 *grid_d,
+                     void *stream) {
+  if (!plan) return fail(IDG_EINVAL, "idg_add_subgrids: plan is NULL");
+  const idg::HostPlan &h = plan->host;
+  const int64_t P = int64_t(h.subgrids.size());
+  if (first < 0 || count < 0 || first + count > P || count > (int64_t(1) << 31) - 1)
+    return fail(IDG_EINVAL, "idg_add_subgrids: bad range");
+  if (count == 0) return IDG_OK;
+  if (!subgrids_d || !grid_d) return fail(IDG_EINVAL, "idg_add_subgrids: NULL device pointer");
+  DevPlan *dp = nullptr;
+  int rc = device_plan(plan, &dp);
+  if (rc != IDG_OK) return rc;
+  const idg_params &p = h.params;
+  TileLists tl;
+  try {
+    build_tile_lists(h.subgrids, first, count, p.grid_size, p.subgrid_size, tl);
+  } catch (const std::bad_alloc &) {
+    return fail(IDG_ENOMEM, "idg_add_subgrids: out of host memory");
+  }
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t *buf = nullptr;
+  const size_t n_ids = tl.tile_ids.size(), n_start = tl.tile_start.size(), n_con = tl.contrib.size();
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&buf), (n_ids + n_start + n_con) * sizeof(int32_t), s),
+          "idg_add_subgrids: allocation");
+  hipError_t err = hipMemcpyAsync(buf, tl.tile_ids.data(), n_ids * 4, hipMemcpyHostToDevice, s);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(buf + n_ids, tl.tile_start.data(), n_start * 4, hipMemcpyHostToDevice, s);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(buf + n_ids + n_start, tl.contrib.data(), n_con * 4, hipMemcpyHostToDevice, s);
+  if (err == hipSuccess) {
+    idg::AdderArgs ad;
+    ad.subgrids = dp->subgrids;
+    ad.first = first;
+    ad.tile_ids = buf;
+    ad.tile_start = buf + n_ids;
+    ad.contrib = buf + n_ids + n_start;
+    ad.subgrids_in = reinterpret_cast<const float2 *>(subgrids_d);
+    ad.grid = reinterpret_cast<float2 *>(grid_d);
+    ad.ntiles = int32_t(n_ids);
+    ad.ntx = (p.grid_size + idg::kAdderTile - 1) / idg::kAdderTile;
+    ad.grid_size = p.grid_size;
+    err = idg::launch_adder(p.subgrid_size, ad, s);
+  }
+  // the host lists must outlive the copies
+  hipError_t es = hipStreamSynchronize(s);
+  hipError_t ef = hipFreeAsync(buf, s);
+  if (err != hipSuccess) return hip_fail(err, "idg_add_subgrids");
+  HIP_TRY(es, "idg_add_subgrids: synchronize");
+  HIP_TRY(ef, "idg_add_subgrids: release");
+  return IDG_OK;
+}
+
+int idg_split_subgrids(idg_plan_t plan, const idg_cf32 *grid_d, int64_t first, int64_t count, idg_cf32 *subgrids_d,
+                       void *stream) {
+  if (!plan) return fail(IDG_EINVAL, "idg_split_subgrids: plan is NULL");
+  const int64_t P = int64_t(plan->host.subgrids.size());
+  if (first < 0 || count < 0 || first + count > P || count > (int64_t(1) << 31) - 1)
+    return fail(IDG_EINVAL, "idg_split_subgrids: bad range");
+  if (count == 0) return IDG_OK;
+  if (!subgrids_d || !grid_d) return fail(IDG_EINVAL, "idg_split_subgrids: NULL device pointer");
+  DevPlan *dp = nullptr;
+  int rc = device_plan(plan, &dp);
+  if (rc != IDG_OK) return rc;
+  const idg_params &p = plan->host.params;
+  HIP_TRY(idg::launch_splitter(p.subgrid_size, dp->subgrids, first, count, reinterpret_cast<const float2 *>(grid_d),
+                               p.grid_size, reinterpret_cast<float2 *>(subgrids_d), static_cast<hipStream_t>(stream)),
+          "idg_split_subgrids: launch");
+  return IDG_OK;
+}
+
+int idg_profile(int enable) {
+  Profiler &p = profiler();
+  std::lock_guard<std::mutex> lock(p.mu);
+  p.on = enable != 0;
+  return IDG_OK;
+}
+
+int idg_profile_read(double *ms, int64_t *launches, int reset) {
+  Profiler &p = profiler();
+  std::vector<Profiler::Rec> recs;
+  {
+    std::lock_guard<std::mutex> lock(p.mu);
+    recs.swap(p.pending);
+  }
+  hipError_t err = hipSuccess;
+  double add_ms[IDG_NR_STAGES] = {};
+  int64_t add_n[IDG_NR_STAGES] = {};
+  for (auto &r : recs) {
+    float t = 0.0f;
+    hipError_t e = hipEventSynchronize(r.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.start, r.stop);
+    if (e == hipSuccess) {
+      add_ms[r.stage] += t;
+      add_n[r.stage] += 1;
+    } else if (err == hipSuccess) {
+      err = e;
+    }
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  std::lock_guard<std::mutex> lock(p.mu);
+  for (int i = 0; i < IDG_NR_STAGES; ++i) {
+    p.ms[i] += add_ms[i];
+    p.launches[i] += add_n[i];
+    if (ms) ms[i] = p.ms[i];
+    if (launches) launches[i] = p.launches[i];
+    if (reset) {
+      p.ms[i] = 0.0;
+      p.launches[i] = 0;
+    }
+  }
+  if (err != hipSuccess) return hip_fail(err, "idg_profile_read");
+  return IDG_OK;
+}
+
+int idg_sync(void *stream) {
+  HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "idg_sync");
+  HIP_TRY(hipGetLastError(), "idg_sync");
+  return IDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Shared between the C-ABI implementation (api.cpp) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "idg.h"
+
+namespace idg {
+
+// Device copy of one subgrid record.
+struct alignas(16) DevSubgrid {
+  int32_t bl, t0, c0, nvis;
+  int32_t x0, y0;
+  int32_t a1, a2;      // Jones block index (slot * nr_stations + station) of stations s1, s2
+  int64_t vis_offset;  // first packed sample of this subgrid
+  int64_t pad;
+};
+static_assert(sizeof(DevSubgrid) == 48, "DevSubgrid layout");
+
+// Arguments of the gridder / degridder kernels.
+struct KernelArgs {
+  const DevSubgrid *subgrids;  // plan subgrids (device)
+  const uint32_t *samples;     // packed (dt << 16 | dc) per planned sample
+  const double *uvw;           // [nbl][nt][3] metres
+  const double *freqs;         // [nch] Hz
+  const float2 *vis_in;        // gridder: [nbl][nt][nch][4]
+  float2 *vis_out;             // degridder: [nbl][nt][nch][4]
+  const float2 *aterms;        // [nslot][nst][L*L][4]
+  const float *taper;          // [L*L]
+  const float4 *lmn;           // [L*L] (l, m, n', 0) float32 from float64
+  const float2 *twiddle;       // [L] exp(-2 pi i k / L)
+  const float2 *grid_in;       // degridder: [4][N][N]
+  float2 *subgrids_out;        // gridder: [count][4][L*L]
+  int64_t first;               // first plan subgrid of this launch
+  int32_t count;               // subgrids in this launch
+  int32_t nr_timesteps, nr_channels;
+  int32_t grid_size;
+  double image_size;
+  int32_t stage;       // gridder: 0 = image after A-terms and taper, 1 = after the DFT
+  int32_t phase_fp32;  // 1: subgrid offsets in float32 (precision study)
+};
+
+// Adder tile: TILE x TILE pixels of one polarisation.
+constexpr int kAdderTile = 32;
+
+struct AdderArgs {
+  const DevSubgrid *subgrids;  // plan subgrids (device)
+  int64_t first;               // plan index of local subgrid 0
+  const int32_t *tile_ids;     // [ntiles] ty * ntx + tx
+  const int32_t *tile_start;   // [ntiles + 1] into contrib
+  const int32_t *contrib;      // local subgrid indices, ascending per tile
+  const float2 *subgrids_in;   // [count][4][L*L]
+  float2 *grid;                // [4][N][N]
+  int32_t ntiles, ntx, grid_size;
+};
+
+bool supported_subgrid_size(int L);
+
+hipError_t launch_gridder(int L, const KernelArgs &a, hipStream_t s);
+hipError_t launch_degridder(int L, const KernelArgs &a, hipStream_t s);
+hipError_t launch_adder(int L, const AdderArgs &a, hipStream_t s);
+hipError_t launch_splitter(int L, const DevSubgrid *subgrids, int64_t first, int64_t count, const float2 *grid,
+                           int grid_size, float2 *out, hipStream_t s);
+hipError_t launch_subgrid_fft(int L, float2 *data, int64_t count, int direction, const float2 *twiddle,
+                              hipStream_t s);
+hipError_t launch_zero_samples(const int64_t *ids, int64_t n, float2 *vis, hipStream_t s);
+
+}  // namespace idg

@@ -1,0 +1,544 @@
+// gfx950 kernels of image-domain gridding.
+//
+//   gridder    direct image-domain sum of a subgrid's visibilities (§3.3 eq.
+//              ShiftedDirectImaging; Algorithm 1 inner loops), A-terms x taper
+//              per pixel (§3.5), centred DFT in LDS (Algorithm 1 "FFT")
+//   adder      sum of transformed subgrids into the master grid, one
+//              workgroup per grid tile and polarisation (Algorithm 1, add)
+//   degridder  splitter, inverse centred DFT, A-terms x taper, and the
+//              per-visibility sum over pixels (Algorithm 2)
+//
+// The phasor sum is not a dense contraction (each term needs its own
+// sin/cos), so it runs on the VALU: float32 phase per (visibility, pixel)
+// from float64 per-subgrid offsets, v_sin_f32 / v_cos_f32 on the phase in
+// revolutions, and float32 multiply-adds.
+#include "internal.h"
+
+#include <algorithm>
+
+namespace idg {
+
+constexpr double kC0 = 299792458.0;
+
+template <int L>
+struct Cfg;
+template <>
+struct Cfg<8> {
+  static constexpr int NT = 64;
+};
+template <>
+struct Cfg<16> {
+  static constexpr int NT = 64;
+};
+template <>
+struct Cfg<24> {
+  static constexpr int NT = 192;
+};
+template <>
+struct Cfg<32> {
+  static constexpr int NT = 256;
+};
+template <>
+struct Cfg<48> {
+  static constexpr int NT = 576;
+};
+template <>
+struct Cfg<64> {
+  static constexpr int NT = 512;
+};
+
+bool supported_subgrid_size(int L) {
+  return L == 8 || L == 16 || L == 24 || L == 32 || L == 48 || L == 64;
+}
+
+// ---------------------------------------------------------------------------
+// small complex helpers
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cjmul(float2 a, float2 b) {  // conj(a) * b
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// Per-pixel polarised kernel for gridding: c * J1^H S J2 (S = [[s0, s1], [s2, s3]]).
+__device__ __forceinline__ void apply_aterms_grid(const float2 *j1, const float2 *j2, float c, float2 s[4]) {
+  const float2 t00 = cadd(cmul(s[0], j2[0]), cmul(s[1], j2[2]));
+  const float2 t01 = cadd(cmul(s[0], j2[1]), cmul(s[1], j2[3]));
+  const float2 t10 = cadd(cmul(s[2], j2[0]), cmul(s[3], j2[2]));
+  const float2 t11 = cadd(cmul(s[2], j2[1]), cmul(s[3], j2[3]));
+  s[0] = cscale(cadd(cjmul(j1[0], t00), cjmul(j1[2], t10)), c);
+  s[1] = cscale(cadd(cjmul(j1[0], t01), cjmul(j1[2], t11)), c);
+  s[2] = cscale(cadd(cjmul(j1[1], t00), cjmul(j1[3], t10)), c);
+  s[3] = cscale(cadd(cjmul(j1[1], t01), cjmul(j1[3], t11)), c);
+}
+
+// Per-pixel polarised kernel for degridding: c * J1 I J2^H.
+__device__ __forceinline__ void apply_aterms_degrid(const float2 *j1, const float2 *j2, float c, float2 s[4]) {
+  const float2 t00 = cadd(cmulc(s[0], j2[0]), cmulc(s[1], j2[1]));
+  const float2 t01 = cadd(cmulc(s[0], j2[2]), cmulc(s[1], j2[3]));
+  const float2 t10 = cadd(cmulc(s[2], j2[0]), cmulc(s[3], j2[1]));
+  const float2 t11 = cadd(cmulc(s[2], j2[2]), cmulc(s[3], j2[3]));
+  s[0] = cscale(cadd(cmul(j1[0], t00), cmul(j1[1], t10)), c);
+  s[1] = cscale(cadd(cmul(j1[0], t01), cmul(j1[1], t11)), c);
+  s[2] = cscale(cadd(cmul(j1[2], t00), cmul(j1[3], t10)), c);
+  s[3] = cscale(cadd(cmul(j1[2], t01), cmul(j1[3], t11)), c);
+}
+
+// ---------------------------------------------------------------------------
+// Centred 2-D DFT of a [4][L][L] subgrid held in LDS, in place:
+//   out[b][a] = sum_{j,i} in[j][i] w((a - L/2)(i - L/2)) w((b - L/2)(j - L/2)),
+// w(k) = exp(dir * 2 pi i k / L); the twiddle table holds exp(-2 pi i k / L).
+// Rows first, then columns; each thread keeps its outputs in registers until
+// every thread has finished reading.
+template <int L, int NT>
+__device__ __forceinline__ void lds_centred_dft(float2 *sg, const float2 *tw, bool inverse) {
+  constexpr int NPIX = L * L, PPT = NPIX / NT, H = L / 2;
+  const int tid = threadIdx.x;
+  const float sgn = inverse ? -1.0f : 1.0f;
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    float2 res[PPT][4];
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      const int pix = tid + r * NT;
+      const int row = pix / L, col = pix % L;
+      // pass 0: transform along a row (output column index `col`, summing over columns)
+      // pass 1: transform along a column (output row index `row`, summing over rows)
+      const int kout = (pass == 0 ? col : row) - H;
+      int idx = (kout * -H) % L;
+      if (idx < 0) idx += L;
+      float2 acc[4] = {};
+#pragma unroll 8
+      for (int q = 0; q < L; ++q) {
+        float2 w = tw[idx];
+        w.y *= sgn;
+        const int src = pass == 0 ? row * L + q : q * L + col;
+#pragma unroll
+        for (int pol = 0; pol < 4; ++pol) {
+          const float2 x = sg[pol * NPIX + src];
+          acc[pol].x += x.x * w.x - x.y * w.y;
+          acc[pol].y += x.x * w.y + x.y * w.x;
+        }
+        idx += kout;
+        idx = idx >= L ? idx - L : (idx < 0 ? idx + L : idx);
+      }
+#pragma unroll
+      for (int pol = 0; pol < 4; ++pol) res[r][pol] = acc[pol];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PPT; ++r)
+#pragma unroll
+      for (int pol = 0; pol < 4; ++pol) sg[pol * NPIX + tid + r * NT] = res[r][pol];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gridder: one workgroup per subgrid, PPT pixels per thread.
+
+template <int L, bool FP32_PHASE>
+__global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT;
+  constexpr int CH = NT < 256 ? NT : 256;  // visibilities staged per round
+  constexpr int SG_BYTES = 4 * NPIX * 8, STAGE_BYTES = CH * 48;
+  constexpr int RAW = SG_BYTES > STAGE_BYTES ? SG_BYTES : STAGE_BYTES;
+  __shared__ float4 raw[RAW / 16];
+  __shared__ float2 s_tw[L];
+  float4 *s_uvw = raw;                        // [CH]
+  float4 *s_vis = raw + CH;                   // [CH][2]
+  float2 *s_sg = reinterpret_cast<float2 *>(raw);  // [4][NPIX], after the visibility loop
+
+  const int tid = threadIdx.x;
+  const DevSubgrid d = a.subgrids[a.first + blockIdx.x];
+  if (tid < L) s_tw[tid] = a.twiddle[tid];
+
+  float pl[PPT], pm[PPT], pn[PPT], p0[PPT];
+  const double S = a.image_size;
+  const double u0 = double(d.x0 + L / 2 - a.grid_size / 2) / S;
+  const double v0 = double(d.y0 + L / 2 - a.grid_size / 2) / S;
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const float4 q = a.lmn[tid + r * NT];
+    pl[r] = q.x;
+    pm[r] = q.y;
+    pn[r] = q.z;
+    p0[r] = FP32_PHASE ? float(u0) * q.x + float(v0) * q.y : 0.0f;
+  }
+
+  float2 acc[PPT][4];
+#pragma unroll
+  for (int r = 0; r < PPT; ++r)
+#pragma unroll
+    for (int pol = 0; pol < 4; ++pol) acc[r][pol] = make_float2(0.0f, 0.0f);
+
+  for (int k0 = 0; k0 < d.nvis; k0 += CH) {
+    const int nk = min(CH, d.nvis - k0);
+    if (tid < nk) {
+      const uint32_t pk = a.samples[d.vis_offset + k0 + tid];
+      const int t = d.t0 + int(pk >> 16), c = d.c0 + int(pk & 0xffffu);
+      const int64_t bt = int64_t(d.bl) * a.nr_timesteps + t;
+      const double *q = a.uvw + bt * 3;
+      const double s = a.freqs[c] / kC0;
+      float4 o;
+      if (FP32_PHASE) {
+        const float sf = float(s);
+        o = make_float4(float(q[0]) * sf, float(q[1]) * sf, float(q[2]) * sf, 0.0f);
+      } else {
+        o = make_float4(float(q[0] * s - u0), float(q[1] * s - v0), float(q[2] * s), 0.0f);
+      }
+      s_uvw[tid] = o;
+      const float4 *vp = reinterpret_cast<const float4 *>(a.vis_in + (bt * a.nr_channels + c) * 4);
+      s_vis[2 * tid] = vp[0];
+      s_vis[2 * tid + 1] = vp[1];
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int k = 0; k < nk; ++k) {
+      const float4 o = s_uvw[k];
+      const float4 v01 = s_vis[2 * k], v23 = s_vis[2 * k + 1];
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        float ph = o.x * pl[r] + o.y * pm[r] + o.z * pn[r];
+        if (FP32_PHASE) ph -= p0[r];
+        ph = __builtin_amdgcn_fractf(ph);
+        const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+        acc[r][0].x += v01.x * cs - v01.y * sn;
+        acc[r][0].y += v01.x * sn + v01.y * cs;
+        acc[r][1].x += v01.z * cs - v01.w * sn;
+        acc[r][1].y += v01.z * sn + v01.w * cs;
+        acc[r][2].x += v23.x * cs - v23.y * sn;
+        acc[r][2].y += v23.x * sn + v23.y * cs;
+        acc[r][3].x += v23.z * cs - v23.w * sn;
+        acc[r][3].y += v23.z * sn + v23.w * cs;
+      }
+    }
+    __syncthreads();
+  }
+
+  // A-terms x taper per pixel, into LDS for the transform
+  const float2 *j1 = a.aterms + int64_t(d.a1) * NPIX * 4;
+  const float2 *j2 = a.aterms + int64_t(d.a2) * NPIX * 4;
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int pix = tid + r * NT;
+    float2 J1[4], J2[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      J1[e] = j1[pix * 4 + e];
+      J2[e] = j2[pix * 4 + e];
+    }
+    apply_aterms_grid(J1, J2, a.taper[pix], acc[r]);
+#pragma unroll
+    for (int pol = 0; pol < 4; ++pol) s_sg[pol * NPIX + pix] = acc[r][pol];
+  }
+  __syncthreads();
+  if (a.stage == 1) lds_centred_dft<L, NT>(s_sg, s_tw, false);
+
+  float2 *out = a.subgrids_out + int64_t(blockIdx.x) * 4 * NPIX;
+#pragma unroll
+  for (int r = 0; r < PPT; ++r)
+#pragma unroll
+    for (int pol = 0; pol < 4; ++pol) out[pol * NPIX + tid + r * NT] = s_sg[pol * NPIX + tid + r * NT];
+}
+
+// ---------------------------------------------------------------------------
+// Degridder: one workgroup per subgrid.  Split + inverse DFT + A-terms into
+// LDS, then each thread evaluates whole visibilities; when a subgrid has few
+// visibilities the pixels are split over G thread groups and summed in LDS.
+
+template <int L, bool FP32_PHASE>
+__global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT;
+  constexpr bool LMN_LDS = L <= 48;  // at L = 64 the pixel coordinates are read through the cache
+  __shared__ float2 s_sg[4 * NPIX];  // [4][NPIX], then [NPIX][4] after the A-terms
+  __shared__ float4 s_lmn[LMN_LDS ? NPIX : 1];
+  __shared__ float2 s_tw[L];
+  __shared__ float4 s_part[NT * 2];  // partial sums of pixel groups
+
+  const int tid = threadIdx.x;
+  const DevSubgrid d = a.subgrids[a.first + blockIdx.x];
+  if (tid < L) s_tw[tid] = a.twiddle[tid];
+  const int N = a.grid_size;
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int pix = tid + r * NT;
+    const int row = pix / L, col = pix % L;
+#pragma unroll
+    for (int pol = 0; pol < 4; ++pol)
+      s_sg[pol * NPIX + pix] = a.grid_in[(int64_t(pol) * N + d.y0 + row) * N + d.x0 + col];
+    if (LMN_LDS) s_lmn[pix] = a.lmn[pix];
+  }
+  __syncthreads();
+  lds_centred_dft<L, NT>(s_sg, s_tw, true);
+
+  const float2 *j1 = a.aterms + int64_t(d.a1) * NPIX * 4;
+  const float2 *j2 = a.aterms + int64_t(d.a2) * NPIX * 4;
+  float2 b[PPT][4];
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int pix = tid + r * NT;
+    float2 J1[4], J2[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      J1[e] = j1[pix * 4 + e];
+      J2[e] = j2[pix * 4 + e];
+      b[r][e] = s_sg[e * NPIX + pix];
+    }
+    apply_aterms_degrid(J1, J2, a.taper[pix], b[r]);
+  }
+  __syncthreads();
+  float4 *s_b = reinterpret_cast<float4 *>(s_sg);  // [NPIX][2] = 4 complex per pixel
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int pix = tid + r * NT;
+    s_b[2 * pix] = make_float4(b[r][0].x, b[r][0].y, b[r][1].x, b[r][1].y);
+    s_b[2 * pix + 1] = make_float4(b[r][2].x, b[r][2].y, b[r][3].x, b[r][3].y);
+  }
+  __syncthreads();
+
+  // pixel groups: G groups of NT / G threads (G a power of two, groups of >= 64 threads)
+  int G = 1;
+  while (G * 2 <= NT / 64 && (NPIX % (G * 2)) == 0 && d.nvis <= NT / (G * 2)) G *= 2;
+  const int nvt = NT / G;
+  const int g = tid / nvt, v = tid % nvt;
+  const int pix_lo = g * (NPIX / G), pix_hi = pix_lo + NPIX / G;
+  const double S = a.image_size;
+  const double u0 = double(d.x0 + L / 2 - N / 2) / S;
+  const double v0 = double(d.y0 + L / 2 - N / 2) / S;
+  const float u0f = float(u0), v0f = float(v0);
+  const int rounds = (d.nvis + nvt - 1) / nvt;
+  for (int it = 0; it < rounds; ++it) {
+    const int k = it * nvt + v;
+    const bool valid = k < d.nvis;
+    float du = 0.0f, dv = 0.0f, w = 0.0f;
+    int64_t out_idx = 0;
+    if (valid) {
+      const uint32_t pk = a.samples[d.vis_offset + k];
+      const int t = d.t0 + int(pk >> 16), c = d.c0 + int(pk & 0xffffu);
+      const int64_t bt = int64_t(d.bl) * a.nr_timesteps + t;
+      const double *q = a.uvw + bt * 3;
+      const double s = a.freqs[c] / kC0;
+      if (FP32_PHASE) {
+        const float sf = float(s);
+        du = float(q[0]) * sf;
+        dv = float(q[1]) * sf;
+        w = float(q[2]) * sf;
+      } else {
+        du = float(q[0] * s - u0);
+        dv = float(q[1] * s - v0);
+        w = float(q[2] * s);
+      }
+      out_idx = (bt * a.nr_channels + c) * 4;
+    }
+    float2 y[4] = {};
+#pragma unroll 2
+    for (int pix = pix_lo; pix < pix_hi; ++pix) {
+      const float4 q = LMN_LDS ? s_lmn[pix] : a.lmn[pix];
+      float ph = du * q.x + dv * q.y + w * q.z;
+      if (FP32_PHASE) ph -= u0f * q.x + v0f * q.y;
+      ph = __builtin_amdgcn_fractf(ph);
+      const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+      const float4 b01 = s_b[2 * pix], b23 = s_b[2 * pix + 1];
+      // y += B * exp(-i phase) = B * (cs - i sn)
+      y[0].x += b01.x * cs + b01.y * sn;
+      y[0].y += b01.y * cs - b01.x * sn;
+      y[1].x += b01.z * cs + b01.w * sn;
+      y[1].y += b01.w * cs - b01.z * sn;
+      y[2].x += b23.x * cs + b23.y * sn;
+      y[2].y += b23.y * cs - b23.x * sn;
+      y[3].x += b23.z * cs + b23.w * sn;
+      y[3].y += b23.w * cs - b23.z * sn;
+    }
+    if (G == 1) {
+      if (valid) {
+        float4 *o = reinterpret_cast<float4 *>(a.vis_out + out_idx);
+        o[0] = make_float4(y[0].x, y[0].y, y[1].x, y[1].y);
+        o[1] = make_float4(y[2].x, y[2].y, y[3].x, y[3].y);
+      }
+    } else {
+      s_part[2 * tid] = make_float4(y[0].x, y[0].y, y[1].x, y[1].y);
+      s_part[2 * tid + 1] = make_float4(y[2].x, y[2].y, y[3].x, y[3].y);
+      __syncthreads();
+      if (g == 0 && valid) {
+        float4 s0 = s_part[2 * v], s1 = s_part[2 * v + 1];
+        for (int gg = 1; gg < G; ++gg) {
+          const float4 p0 = s_part[2 * (gg * nvt + v)], p1 = s_part[2 * (gg * nvt + v) + 1];
+          s0.x += p0.x; s0.y += p0.y; s0.z += p0.z; s0.w += p0.w;
+          s1.x += p1.x; s1.y += p1.y; s1.z += p1.z; s1.w += p1.w;
+        }
+        float4 *o = reinterpret_cast<float4 *>(a.vis_out + out_idx);
+        o[0] = s0;
+        o[1] = s1;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adder: one workgroup per (grid tile, polarisation).  The tile is read once,
+// every subgrid overlapping it is added in plan order, and it is written once.
+
+template <int L>
+__global__ void __launch_bounds__(256) adder_kernel(AdderArgs a) {
+  constexpr int T = kAdderTile, ROWS = 256 / T, PER = T / ROWS, NPIX = L * L;
+  const int tile = a.tile_ids[blockIdx.x];
+  const int pol = blockIdx.y;
+  const int tx = tile % a.ntx, ty = tile / a.ntx;
+  const int N = a.grid_size;
+  const int px = threadIdx.x % T, py = threadIdx.x / T;
+  const int x = tx * T + px;
+  float2 *gp = a.grid + int64_t(pol) * N * N;
+  float2 acc[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int y = ty * T + py + k * ROWS;
+    acc[k] = (x < N && y < N) ? gp[int64_t(y) * N + x] : make_float2(0.0f, 0.0f);
+  }
+  const int c_end = a.tile_start[blockIdx.x + 1];
+  for (int c = a.tile_start[blockIdx.x]; c < c_end; ++c) {
+    const int s = a.contrib[c];
+    const DevSubgrid d = a.subgrids[a.first + s];
+    const int ia = x - d.x0;
+    if (ia < 0 || ia >= L) continue;
+    const float2 *sp = a.subgrids_in + (int64_t(s) * 4 + pol) * NPIX;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int jb = ty * T + py + k * ROWS - d.y0;
+      if (jb >= 0 && jb < L) {
+        const float2 v = sp[jb * L + ia];
+        acc[k].x += v.x;
+        acc[k].y += v.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int y = ty * T + py + k * ROWS;
+    if (x < N && y < N) gp[int64_t(y) * N + x] = acc[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Splitter and the standalone transform.
+
+template <int L>
+__global__ void __launch_bounds__(Cfg<L>::NT) splitter_kernel(const DevSubgrid *subgrids, int64_t first,
+                                                             const float2 *grid, int N, float2 *out) {
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT;
+  const DevSubgrid d = subgrids[first + blockIdx.x];
+  float2 *o = out + int64_t(blockIdx.x) * 4 * NPIX;
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int pix = threadIdx.x + r * NT;
+    const int row = pix / L, col = pix % L;
+#pragma unroll
+    for (int pol = 0; pol < 4; ++pol) o[pol * NPIX + pix] = grid[(int64_t(pol) * N + d.y0 + row) * N + d.x0 + col];
+  }
+}
+
+template <int L>
+__global__ void __launch_bounds__(Cfg<L>::NT) subgrid_fft_kernel(float2 *data, int direction, const float2 *twiddle) {
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT;
+  __shared__ float2 s_sg[4 * NPIX];
+  __shared__ float2 s_tw[L];
+  const int tid = threadIdx.x;
+  if (tid < L) s_tw[tid] = twiddle[tid];
+  float2 *p = data + int64_t(blockIdx.x) * 4 * NPIX;
+#pragma unroll
+  for (int r = 0; r < PPT; ++r)
+#pragma unroll
+    for (int pol = 0; pol < 4; ++pol) s_sg[pol * NPIX + tid + r * NT] = p[pol * NPIX + tid + r * NT];
+  __syncthreads();
+  lds_centred_dft<L, NT>(s_sg, s_tw, direction > 0);
+#pragma unroll
+  for (int r = 0; r < PPT; ++r)
+#pragma unroll
+    for (int pol = 0; pol < 4; ++pol) p[pol * NPIX + tid + r * NT] = s_sg[pol * NPIX + tid + r * NT];
+}
+
+__global__ void zero_samples_kernel(const int64_t *ids, int64_t n, float2 *vis) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    float4 *o = reinterpret_cast<float4 *>(vis + ids[i] * 4);
+    o[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    o[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+#define IDG_DISPATCH_L(L, EXPR)   \
+  switch (L) {                    \
+    case 8: { constexpr int LL = 8; EXPR; break; }   \
+    case 16: { constexpr int LL = 16; EXPR; break; } \
+    case 24: { constexpr int LL = 24; EXPR; break; } \
+    case 32: { constexpr int LL = 32; EXPR; break; } \
+    case 48: { constexpr int LL = 48; EXPR; break; } \
+    case 64: { constexpr int LL = 64; EXPR; break; } \
+    default: return hipErrorInvalidValue;            \
+  }
+
+hipError_t launch_gridder(int L, const KernelArgs &a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  IDG_DISPATCH_L(L, {
+    if (a.phase_fp32)
+      hipLaunchKernelGGL((gridder_kernel<LL, true>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((gridder_kernel<LL, false>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_degridder(int L, const KernelArgs &a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  IDG_DISPATCH_L(L, {
+    if (a.phase_fp32)
+      hipLaunchKernelGGL((degridder_kernel<LL, true>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
+    else
+      hipLaunchKernelGGL((degridder_kernel<LL, false>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_adder(int L, const AdderArgs &a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  IDG_DISPATCH_L(L, { hipLaunchKernelGGL((adder_kernel<LL>), dim3(a.ntiles, 4), dim3(256), 0, s, a); });
+  return hipGetLastError();
+}
+
+hipError_t launch_splitter(int L, const DevSubgrid *subgrids, int64_t first, int64_t count, const float2 *grid,
+                           int grid_size, float2 *out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  IDG_DISPATCH_L(L, {
+    hipLaunchKernelGGL((splitter_kernel<LL>), dim3(unsigned(count)), dim3(Cfg<LL>::NT), 0, s, subgrids, first,
+                       grid, grid_size, out);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_subgrid_fft(int L, float2 *data, int64_t count, int direction, const float2 *twiddle,
+                              hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  IDG_DISPATCH_L(L, {
+    hipLaunchKernelGGL((subgrid_fft_kernel<LL>), dim3(unsigned(count)), dim3(Cfg<LL>::NT), 0, s, data, direction,
+                       twiddle);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_samples(const int64_t *ids, int64_t n, float2 *vis, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(zero_samples_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, ids, n, vis);
+  return hipGetLastError();
+}
+
+}  // namespace idg

@@ -1,0 +1,139 @@
+"""Host-side tests of the C ABI (no GPU calls).
+
+* the library loads and exports every function include/idg.h declares;
+* the library's C++ planner produces exactly the oracle planner's plan
+  (integer-identical subgrid records and sample lists);
+* invalid arguments are rejected with the documented error codes.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.plan import plan_workload
+from tests.util import make_mini, random_track_workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+idg = pytest.importorskip("paper_1909_07226_amd")
+if not os.path.exists(idg.LIB_PATH):
+    pytest.skip("libidg.so not built", allow_module_level=True)
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "idg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(idg_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(idg.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(idg._lib.EXPORTED)
+    assert idg.version() == 10000
+
+
+def _compare(wl):
+    ref = plan_workload(wl)
+    p = idg.Plan.from_workload(wl)
+    st = p.stats()
+    assert st == dict(nr_subgrids=ref.nr_subgrids, nr_gridded=ref.nr_gridded, nr_dropped=ref.nr_dropped,
+                      nr_flagged=ref.nr_flagged)
+    sub, smp = p.export()
+    assert np.array_equal(sub, ref.subgrids)
+    assert np.array_equal(smp.astype(np.int64), ref.samples)
+    return p, ref
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5, 7])
+def test_plan_parity_random_tracks(seed):
+    _compare(random_track_workload(seed=seed, nbl=5, nt=40, nch=4))
+
+
+def test_plan_parity_hand_cases():
+    uvw = np.zeros((1, 20, 3))
+    uvw[0, :, 0] = 2.0 * np.arange(20)
+    for kw in (dict(), dict(tmax=5), dict(aslot=4)):
+        _compare(make_mini(uvw, N=128, L=16, beta=3, **kw))
+    uvw[0, :, 2] = 9.0
+    _compare(make_mini(uvw, N=128, L=16, beta=3))
+    flags = np.zeros((1, 20, 1), np.uint8)
+    flags[0, 7:14] = 1
+    uvw[0, :, 2] = 0.0
+    _compare(make_mini(uvw, N=128, L=16, beta=3, flags=flags))
+
+
+def test_plan_parity_tiny():
+    p, ref = _compare(synth.make_workload("tiny", with_vis=False))
+    assert ref.nr_subgrids == 56
+
+
+def test_plan_parity_skalow_subset_flags():
+    full = synth.make_workload("skalow", with_vis=False)
+    _compare(synth.subset(full, baselines=np.arange(0, full.nr_baselines, 257)))
+
+
+@pytest.mark.slow
+def test_plan_parity_lofar_full():
+    _compare(synth.make_workload("lofar", with_vis=False))
+
+
+def _mini_params(**over):
+    wl = random_track_workload(seed=3)
+    args = dict(grid_size=wl.grid_size, image_size=wl.image_size, subgrid_size=wl.subgrid_size,
+                kernel_size=wl.kernel_size, max_timesteps=wl.max_timesteps, aterm_timesteps=wl.aterm_timesteps,
+                nr_stations=wl.nr_stations, baselines=wl.baselines, uvw=wl.uvw, freqs=wl.freqs)
+    args.update(over)
+    return args
+
+
+@pytest.mark.parametrize("over", [dict(subgrid_size=20), dict(grid_size=63), dict(grid_size=8),
+                                  dict(kernel_size=16), dict(max_timesteps=0), dict(aterm_timesteps=0),
+                                  dict(image_size=0.0), dict(image_size=2.0), dict(nr_stations=1)])
+def test_invalid_params_rejected(over):
+    with pytest.raises(idg.IDGError) as e:
+        idg.Plan(**_mini_params(**over))
+    assert e.value.code == -1
+
+
+def test_invalid_inputs_rejected():
+    args = _mini_params()
+    uvw = args["uvw"].copy()
+    uvw[1, 2, 0] = np.nan
+    with pytest.raises(idg.IDGError) as e:
+        idg.Plan(**dict(args, uvw=uvw))
+    assert e.value.code == -1 and "not finite" in str(e.value)
+    bl = args["baselines"].copy()
+    bl[0] = (2, 2)
+    with pytest.raises(idg.IDGError):
+        idg.Plan(**dict(args, baselines=bl))
+    bl[0] = (0, 99)
+    with pytest.raises(idg.IDGError):
+        idg.Plan(**dict(args, baselines=bl))
+    with pytest.raises(idg.IDGError):
+        idg.Plan(**dict(args, freqs=-args["freqs"]))
+
+
+def test_strict_reports_dropped_samples():
+    uvw = np.zeros((1, 6, 3))
+    uvw[0, :, 0] = 2.0 * np.arange(6)
+    uvw[0, :, 2] = 13.0                       # w-support too large for L = 16: every sample is dropped
+    wl = make_mini(uvw, N=128, L=16, beta=3)
+    p = idg.Plan.from_workload(wl)
+    assert p.stats()["nr_dropped"] == 6
+    with pytest.raises(idg.IDGError) as e:
+        idg.Plan.from_workload(wl, strict=True)
+    assert e.value.code == -4
+
+
+def test_empty_plan():
+    wl = make_mini(np.zeros((2, 0, 3)), N=64, L=16, beta=3)
+    p = idg.Plan.from_workload(wl)
+    assert p.stats() == dict(nr_subgrids=0, nr_gridded=0, nr_dropped=0, nr_flagged=0)

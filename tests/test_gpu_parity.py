@@ -1,0 +1,363 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 oracle.
+
+Every comparison uses the same seeded inputs on both sides.  Stage tests
+(gridder image, gridder after the transform, batched transform, adder,
+splitter) localise a failure; end-to-end tests cover idg_grid / idg_degrid on
+the tiny workload, cut-down LOFAR-like and SKA-low-like workloads (several
+tiles, ragged time blocks, flags), every supported subgrid size, and the
+full-size LOFAR-like workload on sampled outputs and on a property that holds
+at any size.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import idg as oidg
+from oracle.plan import F, plan_workload
+from tests.gpu_common import (ADJOINT_TOL, GRID_MAX_TOL, GRID_RMS_TOL, VIS_RMS_TOL, max_rel, require_gpu, rms_rel,
+                              say, to_dev)
+from tests.util import random_track_workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    require_gpu()
+    import torch
+    import paper_1909_07226_amd as idg
+    return torch, idg
+
+
+def _lofar_subset():
+    full = synth.make_workload("lofar")
+    return synth.subset(full, baselines=np.arange(0, full.nr_baselines, 37), nt=300)
+
+
+def _skalow_subset():
+    full = synth.make_workload("skalow", with_vis=False)
+    wl = synth.subset(full, baselines=np.arange(0, full.nr_baselines, 1021))
+    rng = np.random.default_rng(99)
+    vis = (rng.standard_normal(wl.uvw.shape[:2] + (wl.nr_channels, 4)) * np.sqrt(0.5)
+           + 1j * rng.standard_normal(wl.uvw.shape[:2] + (wl.nr_channels, 4)) * np.sqrt(0.5)).astype(np.complex64)
+    wl.vis = vis
+    return wl
+
+
+CASES = {
+    "tiny": lambda: synth.make_workload("tiny"),
+    "lofar-subset": _lofar_subset,
+    "skalow-subset-flags": _skalow_subset,
+    "tracks-L16-aterms-w": lambda: random_track_workload(seed=5, nbl=6, nt=40, nch=4, random_aterms=True,
+                                                         random_taper=True),
+}
+
+_cache = {}
+
+
+def _case(name):
+    if name not in _cache:
+        wl = CASES[name]()
+        _cache[name] = (wl, plan_workload(wl))
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("stage", [0, 1])
+def test_gridder_subgrids(gpu, name, stage):
+    torch, idg = gpu
+    wl, oplan = _case(name)
+    say(f"[gridder stage {stage}] case={name} subgrids={oplan.nr_subgrids}")
+    plan = idg.Plan.from_workload(wl)
+    d = to_dev(wl)
+    L = wl.subgrid_size
+    P = plan.nr_subgrids
+    ids = np.unique(np.linspace(0, P - 1, min(P, 48)).astype(int))
+    first, count = int(ids[0]), int(ids[-1] - ids[0] + 1)
+    out = torch.zeros((count, 4, L, L), dtype=torch.complex64, device="cuda")
+    idg.grid_subgrids(plan, d["uvw"], d["freqs"], d["vis"], d["aterms"], d["taper"], first, count, stage, out)
+    idg.sync()
+    got = out.cpu().numpy()
+    fn = oidg.grid_subgrid_image if stage == 0 else oidg.grid_subgrid
+    for p in ids:
+        ref = fn(oplan, p, wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)
+        g = got[p - first]
+        assert rms_rel(g, ref) < GRID_RMS_TOL, (name, stage, p, rms_rel(g, ref))
+        assert max_rel(g, ref) < GRID_MAX_TOL, (name, stage, p, max_rel(g, ref))
+
+
+@pytest.mark.parametrize("L", [8, 16, 24, 32, 48, 64])
+@pytest.mark.parametrize("direction", [-1, 1])
+def test_subgrid_transform(gpu, L, direction):
+    torch, idg = gpu
+    say(f"[subgrid transform] L={L} direction={direction}")
+    rng = np.random.default_rng(L + direction)
+    x = (rng.standard_normal((7, 4, L, L)) + 1j * rng.standard_normal((7, 4, L, L))).astype(np.complex64)
+    t = torch.from_numpy(x).cuda()
+    idg.subgrid_fft(t, direction)
+    idg.sync()
+    fn = oidg.forward_subgrid_dft if direction < 0 else oidg.inverse_subgrid_dft
+    for s in range(x.shape[0]):
+        ref = fn(x[s].astype(np.complex128))
+        assert rms_rel(t[s].cpu().numpy(), ref) < 2e-6
+
+
+def test_adder_and_splitter(gpu):
+    torch, idg = gpu
+    wl, oplan = _case("lofar-subset")
+    say(f"[adder/splitter] subgrids={oplan.nr_subgrids}")
+    plan = idg.Plan.from_workload(wl)
+    N, L = wl.grid_size, wl.subgrid_size
+    P = oplan.nr_subgrids
+    rng = np.random.default_rng(7)
+    sub = (rng.standard_normal((P, 4, L, L)) + 1j * rng.standard_normal((P, 4, L, L))).astype(np.complex64)
+    base = np.zeros((4, N, N), np.complex64)
+    base[:, ::7, ::5] = 1.5 - 0.5j
+    g = torch.from_numpy(base).cuda()
+    idg.add_subgrids(plan, torch.from_numpy(sub).cuda(), 0, g)
+    idg.sync()
+    ref = base.astype(np.complex64).copy()
+    for p in range(P):                       # same order as the tile owner: plan order, float32
+        x0, y0 = oplan.subgrids[p, F["x0"]], oplan.subgrids[p, F["y0"]]
+        ref[:, y0:y0 + L, x0:x0 + L] += sub[p]
+    assert np.array_equal(g.cpu().numpy(), ref)          # exact: same additions in the same order
+    # splitter: exact copy
+    out = torch.empty((P, 4, L, L), dtype=torch.complex64, device="cuda")
+    idg.split_subgrids(plan, g, 0, out)
+    idg.sync()
+    gh = g.cpu().numpy()
+    oh = out.cpu().numpy()
+    for p in range(P):
+        x0, y0 = oplan.subgrids[p, F["x0"]], oplan.subgrids[p, F["y0"]]
+        assert np.array_equal(oh[p], gh[:, y0:y0 + L, x0:x0 + L])
+
+
+def _grid_gpu(torch, idg, wl, plan, d, **kw):
+    g = torch.zeros((4, wl.grid_size, wl.grid_size), dtype=torch.complex64, device="cuda")
+    idg.grid(plan, d["uvw"], d["freqs"], d["vis"], d["aterms"], d["taper"], g, **kw)
+    idg.sync()
+    return g
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_grid_end_to_end(gpu, name):
+    torch, idg = gpu
+    wl, oplan = _case(name)
+    say(f"[idg_grid] case={name} subgrids={oplan.nr_subgrids} vis={oplan.nr_gridded}")
+    plan = idg.Plan.from_workload(wl, scratch_bytes=4 * 32 * 1024 * 8 * 9)   # small batches: several adder passes
+    d = to_dev(wl)
+    g = _grid_gpu(torch, idg, wl, plan, d).cpu().numpy()
+    ref = oidg.grid(oplan, wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)
+    say(f"    grid rms rel {rms_rel(g, ref):.2e} max rel {max_rel(g, ref):.2e}")
+    assert rms_rel(g, ref) < GRID_RMS_TOL
+    assert max_rel(g, ref) < GRID_MAX_TOL
+    # untouched pixels stay exactly zero
+    assert np.all(g[ref == 0] == 0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_degrid_end_to_end(gpu, name):
+    torch, idg = gpu
+    wl, oplan = _case(name)
+    say(f"[idg_degrid] case={name} subgrids={oplan.nr_subgrids}")
+    plan = idg.Plan.from_workload(wl)
+    d = to_dev(wl)
+    rng = np.random.default_rng(3)
+    N = wl.grid_size
+    grid_in = np.zeros((4, N, N), np.complex64)
+    # random values on the part of the grid the subgrids cover (elsewhere irrelevant)
+    for p in range(oplan.nr_subgrids):
+        x0, y0, L = oplan.subgrids[p, F["x0"]], oplan.subgrids[p, F["y0"]], wl.subgrid_size
+        grid_in[:, y0:y0 + L, x0:x0 + L] = 1.0
+    mask = grid_in != 0
+    grid_in[mask] = (rng.standard_normal(mask.sum()) + 1j * rng.standard_normal(mask.sum())).astype(np.complex64)
+    vis = torch.full(tuple(wl.vis.shape), 7.0 + 7.0j, dtype=torch.complex64, device="cuda")   # garbage to overwrite
+    idg.degrid(plan, d["uvw"], d["freqs"], torch.from_numpy(grid_in).cuda(), d["aterms"], d["taper"], vis)
+    idg.sync()
+    got = vis.cpu().numpy()
+    ref = oidg.degrid(oplan, wl.uvw, wl.freqs, grid_in, wl.aterms, wl.taper)
+    planned = np.zeros(wl.vis.shape[:3], bool)
+    for p in range(oplan.nr_subgrids):
+        tc = oplan.subgrid_samples(p)
+        planned[oplan.subgrids[p, F["bl"]], tc[:, 0], tc[:, 1]] = True
+    say(f"    vis rms rel {rms_rel(got[planned], ref[planned]):.2e}")
+    assert rms_rel(got[planned], ref[planned]) < VIS_RMS_TOL
+    assert np.all(got[~planned] == 0)      # flagged and dropped samples are written as zero
+
+
+@pytest.mark.parametrize("name", ["tiny", "skalow-subset-flags", "tracks-L16-aterms-w"])
+def test_adjoint_on_gpu(gpu, name):
+    torch, idg = gpu
+    wl, oplan = _case(name)
+    say(f"[adjoint] case={name}")
+    plan = idg.Plan.from_workload(wl)
+    d = to_dev(wl)
+    N = wl.grid_size
+    rng = np.random.default_rng(21)
+    x = (rng.standard_normal((4, N, N)) + 1j * rng.standard_normal((4, N, N))).astype(np.complex64)
+    gy = _grid_gpu(torch, idg, wl, plan, d).cpu().numpy()
+    vx = torch.empty(tuple(wl.vis.shape), dtype=torch.complex64, device="cuda")
+    idg.degrid(plan, d["uvw"], d["freqs"], torch.from_numpy(x).cuda(), d["aterms"], d["taper"], vx)
+    idg.sync()
+    lhs = np.vdot(vx.cpu().numpy().astype(np.complex128), wl.vis.astype(np.complex128))
+    rhs = np.vdot(x.astype(np.complex128), gy.astype(np.complex128))
+    say(f"    adjoint rel {abs(lhs - rhs) / abs(rhs):.2e}")
+    assert abs(lhs - rhs) / abs(rhs) < ADJOINT_TOL
+
+
+def test_grid_is_deterministic(gpu):
+    torch, idg = gpu
+    wl, oplan = _case("lofar-subset")
+    say("[determinism]")
+    plan = idg.Plan.from_workload(wl, scratch_bytes=4 * 32 * 1024 * 8 * 5)
+    d = to_dev(wl)
+    a = _grid_gpu(torch, idg, wl, plan, d)
+    b = _grid_gpu(torch, idg, wl, plan, d)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("L", [8, 16, 24, 32, 48, 64])
+def test_every_subgrid_size(gpu, L):
+    torch, idg = gpu
+    say(f"[subgrid size] L={L}")
+    N = max(128, 4 * L)
+    wl = random_track_workload(seed=L, N=N, L=L, beta=min(7, L // 2 - 1), nbl=3, nt=30, nch=3,
+                               random_aterms=True, random_taper=True)
+    oplan = plan_workload(wl)
+    assert oplan.nr_subgrids > 0
+    plan = idg.Plan.from_workload(wl)
+    d = to_dev(wl)
+    g = _grid_gpu(torch, idg, wl, plan, d).cpu().numpy()
+    ref = oidg.grid(oplan, wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)
+    assert rms_rel(g, ref) < GRID_RMS_TOL
+    vis = torch.empty(tuple(wl.vis.shape), dtype=torch.complex64, device="cuda")
+    idg.degrid(plan, d["uvw"], d["freqs"], torch.from_numpy(ref.astype(np.complex64)).cuda(), d["aterms"],
+               d["taper"], vis)
+    idg.sync()
+    vref = oidg.degrid(oplan, wl.uvw, wl.freqs, ref.astype(np.complex64), wl.aterms, wl.taper)
+    planned = np.abs(vref).sum(-1) > 0
+    assert rms_rel(vis.cpu().numpy()[planned], vref[planned]) < VIS_RMS_TOL
+
+
+def test_edge_subgrids_and_single_sample_blocks(gpu):
+    torch, idg = gpu
+    say("[edges]")
+    # tracks that run into the grid edge (x0 = 0 / x0 + L = N blocks, dropped blocks) and 1-sample blocks
+    N, L = 64, 16
+    uvw = np.zeros((3, 12, 3))
+    uvw[0, :, 0] = -N / 2 + L / 2 + 0.25 * np.arange(12)       # corner at x0 = 0
+    uvw[1, :, 0] = N / 2 - L / 2 - 0.25 * np.arange(12)        # corner at x0 + L = N
+    uvw[2, :, 0] = 3.0 * np.arange(12) - 20                    # fast: blocks of 1-2 samples
+    uvw[:, :, 1] = np.linspace(-20, 20, 3)[:, None]
+    from tests.util import make_mini
+    wl = make_mini(uvw, N=N, L=L, beta=3, tmax=64, random_aterms=True, random_taper=True, seed=8)
+    oplan = plan_workload(wl)
+    assert oplan.subgrids[:, F["x0"]].min() == 0 and (oplan.subgrids[:, F["x0"]] + L).max() == N
+    assert oplan.subgrids[:, F["nvis"]].min() == 1
+    plan = idg.Plan.from_workload(wl)
+    d = to_dev(wl)
+    g = _grid_gpu(torch, idg, wl, plan, d).cpu().numpy()
+    ref = oidg.grid(oplan, wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)
+    assert rms_rel(g, ref) < GRID_RMS_TOL
+
+
+def test_empty_plan_degrid_zeroes(gpu):
+    torch, idg = gpu
+    say("[empty plan]")
+    from tests.util import make_mini
+    uvw = np.zeros((1, 4, 3))
+    uvw[0, :, 2] = 50.0                        # w-support too large: every sample dropped
+    wl = make_mini(uvw, N=64, L=16, beta=3)
+    plan = idg.Plan.from_workload(wl)
+    assert plan.stats()["nr_subgrids"] == 0 and plan.stats()["nr_dropped"] == 4
+    d = to_dev(wl)
+    g = torch.zeros((4, 64, 64), dtype=torch.complex64, device="cuda")
+    idg.grid(plan, d["uvw"], d["freqs"], d["vis"], d["aterms"], d["taper"], g)
+    vis = torch.full((1, 4, 1, 4), 3.0 + 0j, dtype=torch.complex64, device="cuda")
+    idg.degrid(plan, d["uvw"], d["freqs"], g, d["aterms"], d["taper"], vis)
+    idg.sync()
+    assert torch.count_nonzero(g).item() == 0 and torch.count_nonzero(vis).item() == 0
+
+
+# ---------------------------------------------------------------------------
+# full-size LOFAR-like workload (the benchmark configuration)
+
+
+@pytest.fixture(scope="module")
+def lofar_full(gpu):
+    torch, idg = gpu
+    wl = synth.make_workload("lofar")
+    plan = idg.Plan.from_workload(wl)
+    d = to_dev(wl)
+    return wl, plan, d
+
+
+def test_full_lofar_sampled_subgrids(gpu, lofar_full):
+    torch, idg = gpu
+    wl, plan, d = lofar_full
+    say(f"[lofar full] sampled subgrids of {plan.nr_subgrids}")
+    sub, smp = plan.export()
+    from oracle.plan import Plan as OPlan
+    oplan = OPlan(wl.grid_size, wl.image_size, wl.subgrid_size, wl.kernel_size, wl.max_timesteps,
+                  wl.aterm_timesteps, wl.nr_baselines, wl.nr_timesteps, wl.nr_channels, sub, smp.astype(np.int64),
+                  int(sub[:, F["nvis"]].sum()), 0, 0)
+    rng = np.random.default_rng(5)
+    ids = rng.choice(plan.nr_subgrids, 12, replace=False)
+    ids = np.append(ids, np.argmax(sub[:, F["nvis"]]))       # the largest subgrid (several staging rounds)
+    L = wl.subgrid_size
+    out = torch.empty((1, 4, L, L), dtype=torch.complex64, device="cuda")
+    for p in ids:
+        idg.grid_subgrids(plan, d["uvw"], d["freqs"], d["vis"], d["aterms"], d["taper"], int(p), 1, 1, out)
+        idg.sync()
+        ref = oidg.grid_subgrid(oplan, int(p), wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)
+        assert rms_rel(out[0].cpu().numpy(), ref) < GRID_RMS_TOL, p
+
+
+def test_full_lofar_grid_sum_property(gpu, lofar_full):
+    # any size: the sum of a subgrid's uv pixels is L^2 times its image at l = m = 0, i.e.
+    # L^2 c[L/2, L/2] A_s1^H (sum_k Y_k) A_s2 at the centre pixel; summed over all subgrids
+    torch, idg = gpu
+    wl, plan, d = lofar_full
+    say("[lofar full] grid sum property")
+    g = _grid_gpu(torch, idg, wl, plan, d)
+    total = g.to(torch.complex128).sum(dim=(1, 2)).cpu().numpy()
+    sub, smp = plan.export()
+    L = wl.subgrid_size
+    c = float(wl.taper[L // 2, L // 2])
+    ref = np.zeros(4, np.complex128)
+    vis = wl.vis
+    for p in range(sub.shape[0]):
+        bl, off, n = sub[p, F["bl"]], sub[p, F["vis_offset"]], sub[p, F["nvis"]]
+        tc = smp[off:off + n]
+        y = vis[bl, tc[:, 0], tc[:, 1]].astype(np.complex128).sum(0).reshape(2, 2)
+        a1 = wl.aterms[sub[p, F["slot"]], sub[p, F["st1"]], L // 2, L // 2].astype(np.complex128).reshape(2, 2)
+        a2 = wl.aterms[sub[p, F["slot"]], sub[p, F["st2"]], L // 2, L // 2].astype(np.complex128).reshape(2, 2)
+        ref += (np.conj(a1.T) @ y @ a2).reshape(4)
+    ref *= L * L * c
+    say(f"    sum rel err {np.abs(total - ref).max() / np.abs(ref).max():.2e}")
+    assert np.abs(total - ref).max() / np.abs(ref).max() < 1e-5
+
+
+def test_full_lofar_sampled_visibilities(gpu, lofar_full):
+    torch, idg = gpu
+    wl, plan, d = lofar_full
+    say("[lofar full] sampled degridded visibilities")
+    N = wl.grid_size
+    rng = np.random.default_rng(8)
+    gin = torch.complex(torch.randn((4, N, N), generator=torch.Generator().manual_seed(4)),
+                        torch.randn((4, N, N), generator=torch.Generator().manual_seed(5))).to(torch.complex64)
+    gh = gin.numpy()
+    vis = torch.empty(tuple(wl.vis.shape), dtype=torch.complex64, device="cuda")
+    idg.degrid(plan, d["uvw"], d["freqs"], gin.cuda(), d["aterms"], d["taper"], vis)
+    idg.sync()
+    sub, smp = plan.export()
+    from oracle.plan import Plan as OPlan
+    oplan = OPlan(wl.grid_size, wl.image_size, wl.subgrid_size, wl.kernel_size, wl.max_timesteps,
+                  wl.aterm_timesteps, wl.nr_baselines, wl.nr_timesteps, wl.nr_channels, sub, smp.astype(np.int64),
+                  int(sub[:, F["nvis"]].sum()), 0, 0)
+    for p in rng.choice(plan.nr_subgrids, 10, replace=False):
+        ref = oidg.degrid_subgrid(oplan, int(p), wl.uvw, wl.freqs, gh, wl.aterms, wl.taper)
+        tc = oplan.subgrid_samples(int(p))
+        got = vis[int(sub[p, F["bl"]])].cpu().numpy()[tc[:, 0], tc[:, 1]]
+        assert rms_rel(got, ref) < VIS_RMS_TOL, p
