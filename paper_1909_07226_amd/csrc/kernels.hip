@@ -64,6 +64,13 @@ __device__ __forceinline__ float2 cjmul(float2 a, float2 b) {  // conj(a) * b
   return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+// acc += (xr + i xi) * (c + i s) as four fused multiply-adds
+__device__ __forceinline__ void cmac(float2 &acc, float xr, float xi, float c, float s) {
+  acc.x = __builtin_fmaf(xr, c, acc.x);
+  acc.x = __builtin_fmaf(-xi, s, acc.x);
+  acc.y = __builtin_fmaf(xr, s, acc.y);
+  acc.y = __builtin_fmaf(xi, c, acc.y);
+}
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
 // Per-pixel polarised kernel for gridding: c * J1^H S J2 (S = [[s0, s1], [s2, s3]]).
@@ -209,14 +216,11 @@ __global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
         if (FP32_PHASE) ph -= p0[r];
         ph = __builtin_amdgcn_fractf(ph);
         const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-        acc[r][0].x += v01.x * cs - v01.y * sn;
-        acc[r][0].y += v01.x * sn + v01.y * cs;
-        acc[r][1].x += v01.z * cs - v01.w * sn;
-        acc[r][1].y += v01.z * sn + v01.w * cs;
-        acc[r][2].x += v23.x * cs - v23.y * sn;
-        acc[r][2].y += v23.x * sn + v23.y * cs;
-        acc[r][3].x += v23.z * cs - v23.w * sn;
-        acc[r][3].y += v23.z * sn + v23.w * cs;
+        // acc += vis * (cs + i sn), two fused multiply-adds per real output
+        cmac(acc[r][0], v01.x, v01.y, cs, sn);
+        cmac(acc[r][1], v01.z, v01.w, cs, sn);
+        cmac(acc[r][2], v23.x, v23.y, cs, sn);
+        cmac(acc[r][3], v23.z, v23.w, cs, sn);
       }
     }
     __syncthreads();
@@ -250,17 +254,102 @@ __global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
 
 // ---------------------------------------------------------------------------
 // Degridder: one workgroup per subgrid.  Split + inverse DFT + A-terms into
-// LDS, then each thread evaluates whole visibilities; when a subgrid has few
-// visibilities the pixels are split over G thread groups and summed in LDS.
+// LDS, then the visibilities are evaluated in tasks of (64 V visibilities x a
+// 1/G share of the pixels): each lane owns V visibilities, so every broadcast
+// LDS read of a pixel is used V times.  Pixel shares of one visibility are
+// added in LDS at the end.  V and G are chosen per subgrid to fill the waves.
+
+constexpr int kDegridPartCap = 512;  // G * K_p limit of the partial-sum buffer (32 bytes each)
+
+template <int L, int V, bool FP32_PHASE>
+__device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgrid &d, const float4 *s_b,
+                                             const float4 *s_lmn, float4 *s_part, int G, int nchunks, double u0,
+                                             double v0) {
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L, W = NT / 64;
+  constexpr bool LMN_LDS = L <= 48;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const float u0f = float(u0), v0f = float(v0);
+  const int K = d.nvis;
+  for (int task = wave; task < nchunks * G; task += W) {
+    const int chunk = task / G, g = task % G;
+    float du[V], dv[V], w[V];
+    int64_t out_idx[V];
+    bool valid[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int k = (chunk * V + v) * 64 + lane;
+      valid[v] = k < K;
+      du[v] = dv[v] = w[v] = 0.0f;
+      out_idx[v] = 0;
+      if (valid[v]) {
+        const uint32_t pk = a.samples[d.vis_offset + k];
+        const int t = d.t0 + int(pk >> 16), c = d.c0 + int(pk & 0xffffu);
+        const int64_t bt = int64_t(d.bl) * a.nr_timesteps + t;
+        const double *q = a.uvw + bt * 3;
+        const double s = a.freqs[c] / kC0;
+        if (FP32_PHASE) {
+          const float sf = float(s);
+          du[v] = float(q[0]) * sf;
+          dv[v] = float(q[1]) * sf;
+          w[v] = float(q[2]) * sf;
+        } else {
+          du[v] = float(q[0] * s - u0);
+          dv[v] = float(q[1] * s - v0);
+          w[v] = float(q[2] * s);
+        }
+        out_idx[v] = (bt * a.nr_channels + c) * 4;
+      }
+    }
+    float2 y[V][4];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int pol = 0; pol < 4; ++pol) y[v][pol] = make_float2(0.0f, 0.0f);
+    const int lo = g * (NPIX / G), hi = lo + NPIX / G;
+#pragma unroll 2
+    for (int pix = lo; pix < hi; ++pix) {
+      const float4 q = LMN_LDS ? s_lmn[pix] : a.lmn[pix];
+      const float4 b01 = s_b[2 * pix], b23 = s_b[2 * pix + 1];
+      const float off = FP32_PHASE ? u0f * q.x + v0f * q.y : 0.0f;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        float ph = du[v] * q.x + dv[v] * q.y + w[v] * q.z;
+        if (FP32_PHASE) ph -= off;
+        ph = __builtin_amdgcn_fractf(ph);
+        const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
+        // y += B * exp(-i phase) = B * (cs - i sn)
+        cmac(y[v][0], b01.x, b01.y, cs, -sn);
+        cmac(y[v][1], b01.z, b01.w, cs, -sn);
+        cmac(y[v][2], b23.x, b23.y, cs, -sn);
+        cmac(y[v][3], b23.z, b23.w, cs, -sn);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      if (!valid[v]) continue;
+      const float4 r0 = make_float4(y[v][0].x, y[v][0].y, y[v][1].x, y[v][1].y);
+      const float4 r1 = make_float4(y[v][2].x, y[v][2].y, y[v][3].x, y[v][3].y);
+      if (G == 1) {
+        float4 *o = reinterpret_cast<float4 *>(a.vis_out + out_idx[v]);
+        o[0] = r0;
+        o[1] = r1;
+      } else {
+        const int k = (chunk * V + v) * 64 + lane;
+        s_part[2 * (g * K + k)] = r0;
+        s_part[2 * (g * K + k) + 1] = r1;
+      }
+    }
+  }
+}
 
 template <int L, bool FP32_PHASE>
 __global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
-  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT;
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT, W = NT / 64;
   constexpr bool LMN_LDS = L <= 48;  // at L = 64 the pixel coordinates are read through the cache
   __shared__ float2 s_sg[4 * NPIX];  // [4][NPIX], then [NPIX][4] after the A-terms
   __shared__ float4 s_lmn[LMN_LDS ? NPIX : 1];
   __shared__ float2 s_tw[L];
-  __shared__ float4 s_part[NT * 2];  // partial sums of pixel groups
+  __shared__ float4 s_part[2 * kDegridPartCap];  // [G][K] partial sums, 4 complex each  // partial sums of pixel shares
 
   const int tid = threadIdx.x;
   const DevSubgrid d = a.subgrids[a.first + blockIdx.x];
@@ -303,81 +392,47 @@ __global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
   }
   __syncthreads();
 
-  // pixel groups: G groups of NT / G threads (G a power of two, groups of >= 64 threads)
-  int G = 1;
-  while (G * 2 <= NT / 64 && (NPIX % (G * 2)) == 0 && d.nvis <= NT / (G * 2)) G *= 2;
-  const int nvt = NT / G;
-  const int g = tid / nvt, v = tid % nvt;
-  const int pix_lo = g * (NPIX / G), pix_hi = pix_lo + NPIX / G;
+  // visibilities per lane V and pixel shares G (a power of two): fill the W waves with tasks first,
+  // then prefer the largest V (fewest LDS reads per visibility)
+  const int K = d.nvis;
+  const int n64 = (K + 63) / 64;
+  int V = 1, G = 1, nchunks = n64, best = -1;
+  for (int vc = 4; vc >= 1; vc /= 2) {
+    if (vc > 1 && n64 < vc) continue;
+    const int nc = (n64 + vc - 1) / vc;
+    int gc = 1;
+    while (2 * gc * nc <= W && 2 * gc * K <= kDegridPartCap && NPIX % (2 * gc) == 0) gc *= 2;
+    const int filled = min(nc * gc, W);
+    if (filled > best) {
+      best = filled;
+      V = vc;
+      G = gc;
+      nchunks = nc;
+    }
+  }
   const double S = a.image_size;
   const double u0 = double(d.x0 + L / 2 - N / 2) / S;
   const double v0 = double(d.y0 + L / 2 - N / 2) / S;
-  const float u0f = float(u0), v0f = float(v0);
-  const int rounds = (d.nvis + nvt - 1) / nvt;
-  for (int it = 0; it < rounds; ++it) {
-    const int k = it * nvt + v;
-    const bool valid = k < d.nvis;
-    float du = 0.0f, dv = 0.0f, w = 0.0f;
-    int64_t out_idx = 0;
-    if (valid) {
+  if (V == 4)
+    degrid_tasks<L, 4, FP32_PHASE>(a, d, s_b, s_lmn, s_part, G, nchunks, u0, v0);
+  else if (V == 2)
+    degrid_tasks<L, 2, FP32_PHASE>(a, d, s_b, s_lmn, s_part, G, nchunks, u0, v0);
+  else
+    degrid_tasks<L, 1, FP32_PHASE>(a, d, s_b, s_lmn, s_part, G, nchunks, u0, v0);
+  if (G > 1) {
+    __syncthreads();
+    for (int k = tid; k < K; k += NT) {
+      float4 s0 = s_part[2 * k], s1 = s_part[2 * k + 1];
+      for (int g = 1; g < G; ++g) {
+        const float4 p0 = s_part[2 * (g * K + k)], p1 = s_part[2 * (g * K + k) + 1];
+        s0.x += p0.x; s0.y += p0.y; s0.z += p0.z; s0.w += p0.w;
+        s1.x += p1.x; s1.y += p1.y; s1.z += p1.z; s1.w += p1.w;
+      }
       const uint32_t pk = a.samples[d.vis_offset + k];
       const int t = d.t0 + int(pk >> 16), c = d.c0 + int(pk & 0xffffu);
-      const int64_t bt = int64_t(d.bl) * a.nr_timesteps + t;
-      const double *q = a.uvw + bt * 3;
-      const double s = a.freqs[c] / kC0;
-      if (FP32_PHASE) {
-        const float sf = float(s);
-        du = float(q[0]) * sf;
-        dv = float(q[1]) * sf;
-        w = float(q[2]) * sf;
-      } else {
-        du = float(q[0] * s - u0);
-        dv = float(q[1] * s - v0);
-        w = float(q[2] * s);
-      }
-      out_idx = (bt * a.nr_channels + c) * 4;
-    }
-    float2 y[4] = {};
-#pragma unroll 2
-    for (int pix = pix_lo; pix < pix_hi; ++pix) {
-      const float4 q = LMN_LDS ? s_lmn[pix] : a.lmn[pix];
-      float ph = du * q.x + dv * q.y + w * q.z;
-      if (FP32_PHASE) ph -= u0f * q.x + v0f * q.y;
-      ph = __builtin_amdgcn_fractf(ph);
-      const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-      const float4 b01 = s_b[2 * pix], b23 = s_b[2 * pix + 1];
-      // y += B * exp(-i phase) = B * (cs - i sn)
-      y[0].x += b01.x * cs + b01.y * sn;
-      y[0].y += b01.y * cs - b01.x * sn;
-      y[1].x += b01.z * cs + b01.w * sn;
-      y[1].y += b01.w * cs - b01.z * sn;
-      y[2].x += b23.x * cs + b23.y * sn;
-      y[2].y += b23.y * cs - b23.x * sn;
-      y[3].x += b23.z * cs + b23.w * sn;
-      y[3].y += b23.w * cs - b23.z * sn;
-    }
-    if (G == 1) {
-      if (valid) {
-        float4 *o = reinterpret_cast<float4 *>(a.vis_out + out_idx);
-        o[0] = make_float4(y[0].x, y[0].y, y[1].x, y[1].y);
-        o[1] = make_float4(y[2].x, y[2].y, y[3].x, y[3].y);
-      }
-    } else {
-      s_part[2 * tid] = make_float4(y[0].x, y[0].y, y[1].x, y[1].y);
-      s_part[2 * tid + 1] = make_float4(y[2].x, y[2].y, y[3].x, y[3].y);
-      __syncthreads();
-      if (g == 0 && valid) {
-        float4 s0 = s_part[2 * v], s1 = s_part[2 * v + 1];
-        for (int gg = 1; gg < G; ++gg) {
-          const float4 p0 = s_part[2 * (gg * nvt + v)], p1 = s_part[2 * (gg * nvt + v) + 1];
-          s0.x += p0.x; s0.y += p0.y; s0.z += p0.z; s0.w += p0.w;
-          s1.x += p1.x; s1.y += p1.y; s1.z += p1.z; s1.w += p1.w;
-        }
-        float4 *o = reinterpret_cast<float4 *>(a.vis_out + out_idx);
-        o[0] = s0;
-        o[1] = s1;
-      }
-      __syncthreads();
+      float4 *o = reinterpret_cast<float4 *>(a.vis_out + ((int64_t(d.bl) * a.nr_timesteps + t) * a.nr_channels + c) * 4);
+      o[0] = s0;
+      o[1] = s1;
     }
   }
 }

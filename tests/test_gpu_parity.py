@@ -246,15 +246,15 @@ def test_edge_subgrids_and_single_sample_blocks(gpu):
     # tracks that run into the grid edge (x0 = 0 / x0 + L = N blocks, dropped blocks) and 1-sample blocks
     N, L = 64, 16
     uvw = np.zeros((3, 12, 3))
-    uvw[0, :, 0] = -N / 2 + L / 2 + 0.25 * np.arange(12)       # corner at x0 = 0
-    uvw[1, :, 0] = N / 2 - L / 2 - 0.25 * np.arange(12)        # corner at x0 + L = N
-    uvw[2, :, 0] = 3.0 * np.arange(12) - 20                    # fast: blocks of 1-2 samples
+    uvw[0, :, 0] = -N / 2 + L / 2 - 0.4 + 0.05 * np.arange(12)  # x 7.6 .. 8.15: centre 8, corner x0 = 0
+    uvw[1, :, 0] = N / 2 - L / 2 + 0.4 - 0.05 * np.arange(12)   # x 56.4 .. 55.85: centre 56, x0 + L = N
+    uvw[2, :, 0] = 13.0 * np.arange(12) - 20                   # fast: 1-sample blocks, then off the grid
     uvw[:, :, 1] = np.linspace(-20, 20, 3)[:, None]
     from tests.util import make_mini
     wl = make_mini(uvw, N=N, L=L, beta=3, tmax=64, random_aterms=True, random_taper=True, seed=8)
     oplan = plan_workload(wl)
     assert oplan.subgrids[:, F["x0"]].min() == 0 and (oplan.subgrids[:, F["x0"]] + L).max() == N
-    assert oplan.subgrids[:, F["nvis"]].min() == 1
+    assert oplan.subgrids[:, F["nvis"]].min() == 1 and oplan.nr_dropped > 0
     plan = idg.Plan.from_workload(wl)
     d = to_dev(wl)
     g = _grid_gpu(torch, idg, wl, plan, d).cpu().numpy()
