@@ -98,52 +98,165 @@ __device__ __forceinline__ void apply_aterms_degrid(const float2 *j1, const floa
 }
 
 // ---------------------------------------------------------------------------
+// Subgrid layout in LDS: [4][L][RS] complex.  Power-of-two sizes are
+// transformed by a register FFT per row / column; their rows are padded to
+// RS = L + 1 so that the lanes of a wave, each walking its own row, hit
+// different LDS banks.
+
+template <int L>
+struct SgLayout {
+  static constexpr bool FFT = (L == 8 || L == 16 || L == 32);
+  static constexpr int RS = FFT ? L + 1 : L;  // row stride
+  static constexpr int POL = L * RS;          // polarisation stride
+  static constexpr int SIZE = 4 * POL;        // complex elements
+  __device__ static __forceinline__ int idx(int pol, int pix) { return pol * POL + (pix / L) * RS + pix % L; }
+};
+
+// exp(-2 pi i k / N), k = 0 .. N-1, evaluated at compile time in double precision
+constexpr double kPi = 3.14159265358979323846;
+constexpr double cx_sin(double x) {  // |x| <= pi
+  double term = x, sum = x;
+  for (int n = 1; n < 16; ++n) {
+    term *= -x * x / double((2 * n) * (2 * n + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_cos(double x) {  // |x| <= pi
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 16; ++n) {
+    term *= -x * x / double((2 * n - 1) * (2 * n));
+    sum += term;
+  }
+  return sum;
+}
+template <int N>
+struct Twiddles {
+  float re[N], im[N];
+  constexpr Twiddles() : re(), im() {
+    for (int k = 0; k < N; ++k) {
+      double a = -2.0 * kPi * k / N;
+      if (a < -kPi) a += 2.0 * kPi;
+      re[k] = float(cx_cos(a));
+      im[k] = float(cx_sin(a));
+    }
+  }
+};
+constexpr int bit_reverse(int i, int n) {
+  int r = 0;
+  for (int b = 1; b < n; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// In-register radix-2 FFT, X[k] = sum_n x[n] exp(-+2 pi i n k / N) (INV: +), unnormalised.
+template <int N, bool INV>
+__device__ __forceinline__ void reg_fft(float2 (&x)[N]) {
+  constexpr Twiddles<N> T{};
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int j = bit_reverse(i, N);
+    if (i < j) {
+      const float2 t = x[i];
+      x[i] = x[j];
+      x[j] = t;
+    }
+  }
+#pragma unroll
+  for (int len = 2; len <= N; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < N; i += len) {
+#pragma unroll
+      for (int k = 0; k < len / 2; ++k) {
+        const int e = k * (N / len);
+        const float2 u = x[i + k], v = x[i + k + len / 2];
+        float2 vw;
+        if (e == 0) {
+          vw = v;
+        } else if (4 * e == N) {  // exp(-+ i pi / 2)
+          vw = INV ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+        } else {
+          const float wr = T.re[e], wi = INV ? -T.im[e] : T.im[e];
+          vw = make_float2(v.x * wr - v.y * wi, v.x * wi + v.y * wr);
+        }
+        x[i + k] = make_float2(u.x + vw.x, u.y + vw.y);
+        x[i + k + len / 2] = make_float2(u.x - vw.x, u.y - vw.y);
+      }
+    }
+  }
+}
+
 // Centred 2-D DFT of a [4][L][L] subgrid held in LDS, in place:
 //   out[b][a] = sum_{j,i} in[j][i] w((a - L/2)(i - L/2)) w((b - L/2)(j - L/2)),
-// w(k) = exp(dir * 2 pi i k / L); the twiddle table holds exp(-2 pi i k / L).
-// Rows first, then columns; each thread keeps its outputs in registers until
-// every thread has finished reading.
-template <int L, int NT>
-__device__ __forceinline__ void lds_centred_dft(float2 *sg, const float2 *tw, bool inverse) {
+// w(k) = exp(-+2 pi i k / L) (INV: +).  For even L this is
+//   out = (-1)^(a+b) FFT2[(-1)^(i+j) in],
+// done as one register FFT per (polarisation, row) and then per (polarisation,
+// column).  Other sizes use a direct DFT per output (twiddle table `tw`).
+template <int L, int NT, bool INV>
+__device__ __forceinline__ void lds_centred_dft(float2 *sg, const float2 *tw) {
+  using Lay = SgLayout<L>;
   constexpr int NPIX = L * L, PPT = NPIX / NT, H = L / 2;
   const int tid = threadIdx.x;
-  const float sgn = inverse ? -1.0f : 1.0f;
+  if constexpr (Lay::FFT) {
 #pragma unroll 1
-  for (int pass = 0; pass < 2; ++pass) {
-    float2 res[PPT][4];
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int line = tid; line < 4 * L; line += NT) {
+        const int pol = line / L, q = line % L;  // q: row (pass 0) or column (pass 1)
+        float2 *base = sg + pol * Lay::POL + (pass == 0 ? q * Lay::RS : q);
+        const int step = pass == 0 ? 1 : Lay::RS;
+        float2 x[L];
 #pragma unroll
-    for (int r = 0; r < PPT; ++r) {
-      const int pix = tid + r * NT;
-      const int row = pix / L, col = pix % L;
-      // pass 0: transform along a row (output column index `col`, summing over columns)
-      // pass 1: transform along a column (output row index `row`, summing over rows)
-      const int kout = (pass == 0 ? col : row) - H;
-      int idx = (kout * -H) % L;
-      if (idx < 0) idx += L;
-      float2 acc[4] = {};
-#pragma unroll 8
-      for (int q = 0; q < L; ++q) {
-        float2 w = tw[idx];
-        w.y *= sgn;
-        const int src = pass == 0 ? row * L + q : q * L + col;
-#pragma unroll
-        for (int pol = 0; pol < 4; ++pol) {
-          const float2 x = sg[pol * NPIX + src];
-          acc[pol].x += x.x * w.x - x.y * w.y;
-          acc[pol].y += x.x * w.y + x.y * w.x;
+        for (int n = 0; n < L; ++n) {
+          const float2 v = base[n * step];
+          const bool flip = pass == 0 && ((n + q) & 1);
+          x[n] = flip ? make_float2(-v.x, -v.y) : v;
         }
-        idx += kout;
-        idx = idx >= L ? idx - L : (idx < 0 ? idx + L : idx);
+        reg_fft<L, INV>(x);
+#pragma unroll
+        for (int k = 0; k < L; ++k) base[k * step] = (k & 1) ? make_float2(-x[k].x, -x[k].y) : x[k];
       }
-#pragma unroll
-      for (int pol = 0; pol < 4; ++pol) res[r][pol] = acc[pol];
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+    const float sgn = INV ? -1.0f : 1.0f;
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+      float2 res[PPT][4];
 #pragma unroll
-    for (int r = 0; r < PPT; ++r)
+      for (int r = 0; r < PPT; ++r) {
+        const int pix = tid + r * NT;
+        const int row = pix / L, col = pix % L;
+        // pass 0: transform along a row (output column `col`); pass 1: along a column (output row `row`)
+        const int kout = (pass == 0 ? col : row) - H;
+        int idx = (kout * -H) % L;
+        if (idx < 0) idx += L;
+        float2 acc[4] = {};
+#pragma unroll 8
+        for (int q = 0; q < L; ++q) {
+          float2 w = tw[idx];
+          w.y *= sgn;
+          const int src = pass == 0 ? row * L + q : q * L + col;
 #pragma unroll
-      for (int pol = 0; pol < 4; ++pol) sg[pol * NPIX + tid + r * NT] = res[r][pol];
-    __syncthreads();
+          for (int pol = 0; pol < 4; ++pol) {
+            const float2 x = sg[pol * NPIX + src];
+            acc[pol].x += x.x * w.x - x.y * w.y;
+            acc[pol].y += x.x * w.y + x.y * w.x;
+          }
+          idx += kout;
+          idx = idx >= L ? idx - L : (idx < 0 ? idx + L : idx);
+        }
+#pragma unroll
+        for (int pol = 0; pol < 4; ++pol) res[r][pol] = acc[pol];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < PPT; ++r)
+#pragma unroll
+        for (int pol = 0; pol < 4; ++pol) sg[pol * NPIX + tid + r * NT] = res[r][pol];
+      __syncthreads();
+    }
   }
 }
 
@@ -154,13 +267,13 @@ template <int L, bool FP32_PHASE>
 __global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT;
   constexpr int CH = NT < 256 ? NT : 256;  // visibilities staged per round
-  constexpr int SG_BYTES = 4 * NPIX * 8, STAGE_BYTES = CH * 48;
+  constexpr int SG_BYTES = SgLayout<L>::SIZE * 8, STAGE_BYTES = CH * 48;
   constexpr int RAW = SG_BYTES > STAGE_BYTES ? SG_BYTES : STAGE_BYTES;
   __shared__ float4 raw[RAW / 16];
   __shared__ float2 s_tw[L];
   float4 *s_uvw = raw;                        // [CH]
   float4 *s_vis = raw + CH;                   // [CH][2]
-  float2 *s_sg = reinterpret_cast<float2 *>(raw);  // [4][NPIX], after the visibility loop
+  float2 *s_sg = reinterpret_cast<float2 *>(raw);  // SgLayout<L>, after the visibility loop
 
   const int tid = threadIdx.x;
   const DevSubgrid d = a.subgrids[a.first + blockIdx.x];
@@ -240,16 +353,16 @@ __global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
     }
     apply_aterms_grid(J1, J2, a.taper[pix], acc[r]);
 #pragma unroll
-    for (int pol = 0; pol < 4; ++pol) s_sg[pol * NPIX + pix] = acc[r][pol];
+    for (int pol = 0; pol < 4; ++pol) s_sg[SgLayout<L>::idx(pol, pix)] = acc[r][pol];
   }
   __syncthreads();
-  if (a.stage == 1) lds_centred_dft<L, NT>(s_sg, s_tw, false);
+  if (a.stage == 1) lds_centred_dft<L, NT, false>(s_sg, s_tw);
 
   float2 *out = a.subgrids_out + int64_t(blockIdx.x) * 4 * NPIX;
 #pragma unroll
   for (int r = 0; r < PPT; ++r)
 #pragma unroll
-    for (int pol = 0; pol < 4; ++pol) out[pol * NPIX + tid + r * NT] = s_sg[pol * NPIX + tid + r * NT];
+    for (int pol = 0; pol < 4; ++pol) out[pol * NPIX + tid + r * NT] = s_sg[SgLayout<L>::idx(pol, tid + r * NT)];
 }
 
 // ---------------------------------------------------------------------------
@@ -346,7 +459,7 @@ template <int L, bool FP32_PHASE>
 __global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT, W = NT / 64;
   constexpr bool LMN_LDS = L <= 48;  // at L = 64 the pixel coordinates are read through the cache
-  __shared__ float2 s_sg[4 * NPIX];  // [4][NPIX], then [NPIX][4] after the A-terms
+  __shared__ float2 s_sg[SgLayout<L>::SIZE];  // SgLayout<L>, then [NPIX][4] after the A-terms
   __shared__ float4 s_lmn[LMN_LDS ? NPIX : 1];
   __shared__ float2 s_tw[L];
   __shared__ float4 s_part[2 * kDegridPartCap];  // [G][K] partial sums, 4 complex each  // partial sums of pixel shares
@@ -361,11 +474,11 @@ __global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
     const int row = pix / L, col = pix % L;
 #pragma unroll
     for (int pol = 0; pol < 4; ++pol)
-      s_sg[pol * NPIX + pix] = a.grid_in[(int64_t(pol) * N + d.y0 + row) * N + d.x0 + col];
+      s_sg[SgLayout<L>::idx(pol, pix)] = a.grid_in[(int64_t(pol) * N + d.y0 + row) * N + d.x0 + col];
     if (LMN_LDS) s_lmn[pix] = a.lmn[pix];
   }
   __syncthreads();
-  lds_centred_dft<L, NT>(s_sg, s_tw, true);
+  lds_centred_dft<L, NT, true>(s_sg, s_tw);
 
   const float2 *j1 = a.aterms + int64_t(d.a1) * NPIX * 4;
   const float2 *j2 = a.aterms + int64_t(d.a2) * NPIX * 4;
@@ -378,7 +491,7 @@ __global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
     for (int e = 0; e < 4; ++e) {
       J1[e] = j1[pix * 4 + e];
       J2[e] = j2[pix * 4 + e];
-      b[r][e] = s_sg[e * NPIX + pix];
+      b[r][e] = s_sg[SgLayout<L>::idx(e, pix)];
     }
     apply_aterms_degrid(J1, J2, a.taper[pix], b[r]);
   }
@@ -499,10 +612,10 @@ __global__ void __launch_bounds__(Cfg<L>::NT) splitter_kernel(const DevSubgrid *
   }
 }
 
-template <int L>
-__global__ void __launch_bounds__(Cfg<L>::NT) subgrid_fft_kernel(float2 *data, int direction, const float2 *twiddle) {
+template <int L, bool INV>
+__global__ void __launch_bounds__(Cfg<L>::NT) subgrid_fft_kernel(float2 *data, const float2 *twiddle) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT;
-  __shared__ float2 s_sg[4 * NPIX];
+  __shared__ float2 s_sg[SgLayout<L>::SIZE];
   __shared__ float2 s_tw[L];
   const int tid = threadIdx.x;
   if (tid < L) s_tw[tid] = twiddle[tid];
@@ -510,13 +623,13 @@ __global__ void __launch_bounds__(Cfg<L>::NT) subgrid_fft_kernel(float2 *data, i
 #pragma unroll
   for (int r = 0; r < PPT; ++r)
 #pragma unroll
-    for (int pol = 0; pol < 4; ++pol) s_sg[pol * NPIX + tid + r * NT] = p[pol * NPIX + tid + r * NT];
+    for (int pol = 0; pol < 4; ++pol) s_sg[SgLayout<L>::idx(pol, tid + r * NT)] = p[pol * NPIX + tid + r * NT];
   __syncthreads();
-  lds_centred_dft<L, NT>(s_sg, s_tw, direction > 0);
+  lds_centred_dft<L, NT, INV>(s_sg, s_tw);
 #pragma unroll
   for (int r = 0; r < PPT; ++r)
 #pragma unroll
-    for (int pol = 0; pol < 4; ++pol) p[pol * NPIX + tid + r * NT] = s_sg[pol * NPIX + tid + r * NT];
+    for (int pol = 0; pol < 4; ++pol) p[pol * NPIX + tid + r * NT] = s_sg[SgLayout<L>::idx(pol, tid + r * NT)];
 }
 
 __global__ void zero_samples_kernel(const int64_t *ids, int64_t n, float2 *vis) {
@@ -583,8 +696,11 @@ hipError_t launch_subgrid_fft(int L, float2 *data, int64_t count, int direction,
                               hipStream_t s) {
   if (count <= 0) return hipSuccess;
   IDG_DISPATCH_L(L, {
-    hipLaunchKernelGGL((subgrid_fft_kernel<LL>), dim3(unsigned(count)), dim3(Cfg<LL>::NT), 0, s, data, direction,
-                       twiddle);
+    if (direction > 0)
+      hipLaunchKernelGGL((subgrid_fft_kernel<LL, true>), dim3(unsigned(count)), dim3(Cfg<LL>::NT), 0, s, data, twiddle);
+    else
+      hipLaunchKernelGGL((subgrid_fft_kernel<LL, false>), dim3(unsigned(count)), dim3(Cfg<LL>::NT), 0, s, data,
+                         twiddle);
   });
   return hipGetLastError();
 }
