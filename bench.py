@@ -91,6 +91,47 @@ def cpu_baseline(wl, budget_s):
             "grid_s": round(t1 - t0, 3), "degrid_s": round(t2 - t1, 3)}
 
 
+def serving_leg(lofar_wl, lofar_dev, n_jobs, log):
+    """Replay one request trace twice: continuous batching (4 slots, persistent form) and a FIFO
+    (1 slot, plain form).  p50/p99 of completion - arrival."""
+    import torch
+    import synth
+    from paper_1909_07226_amd import serve
+    tiny = synth.make_workload("tiny", nt=2048, nch=16)
+    dev = "cuda"
+    tiny_dev = dict(uvw=torch.from_numpy(tiny.uvw).to(dev), freqs=torch.from_numpy(tiny.freqs).to(dev),
+                    vis=torch.from_numpy(tiny.vis).to(dev), aterms=torch.from_numpy(tiny.aterms).to(dev),
+                    taper=torch.from_numpy(tiny.taper).to(dev))
+    g = torch.Generator(device=dev).manual_seed(11)
+    grids = {c: torch.complex(torch.randn((4, n, n), generator=g, device=dev),
+                              torch.randn((4, n, n), generator=g, device=dev)).to(torch.complex64)
+             for c, n in (("tiny", tiny.grid_size), ("lofar", lofar_wl.grid_size))}
+    trace = synth.serving_trace(n_jobs=n_jobs)
+    t = time.perf_counter()
+    jobs, templates = serve.jobs_from_trace(trace, {"tiny": tiny, "lofar": lofar_wl},
+                                            {"tiny": tiny_dev, "lofar": lofar_dev}, grids)
+    log(f"[bench] serving: {len(jobs)} jobs, {len(templates)} plans built in {time.perf_counter() - t:.1f} s")
+    out = {"trace": f"{n_jobs} jobs, Poisson arrivals at 50 jobs/s, 50% grid / 50% degrid, 50% 8-station "
+                    f"(N=512, L=24) / 50% LOFAR-like (N=4096, L=32), nt ~ U{{64..2048}}, nch ~ U{{4..16}}"}
+    # warm-up outside the timed trace: every plan uploads its device metadata once
+    for cls, tp in ((k[0], v) for k, v in templates.items()):
+        for kind in ("grid", "degrid"):
+            j = serve.Job(kind, tp["plan"], tp["uvw"], tp["freqs"], tp["aterms"], tp["taper"], vis=tp["vis"],
+                          grid=grids[cls])
+            j.launch(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for label, slots, form in (("continuous", 4, "persistent"), ("fifo_plain", 1, "plain")):
+        for tp in templates.values():
+            tp["plan"].set_tuning(form=form)
+        with serve.Server(slots=slots, mem_budget=48 << 30) as srv:
+            futs = serve.replay(srv, jobs, trace["arrivals"])
+        summ = serve.latency_summary(futs)
+        summ.update(slots=slots, form=form, failed=sum(1 for f in futs if f._error is not None))
+        out[label] = summ
+        log(f"[bench] serving {label}: {summ}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +140,14 @@ def main():
     ap.add_argument("--workload", default="lofar", choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--form", default="auto", choices=("auto", "plain", "persistent"),
+                    help="gridder/degridder schedule: autotuned (default), one workgroup per subgrid, or a "
+                         "persistent work queue")
+    ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent form: workgroups per CU (0 = max)")
+    ap.add_argument("--adder-chunk", type=int, default=0, help="adder: longest tile-list run per workgroup (0 = 256)")
+    ap.add_argument("--serve-jobs", type=int, default=400, help="jobs in the serving trace (0 = skip serving)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="finish with a plain device copy of BYTES (reference for HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -136,23 +185,34 @@ def main():
         idg.grid(plan, uvw, freqs, vis, aterms, taper, grid, stream)
         idg.degrid(plan, uvw, freqs, grid, aterms, taper, vis_out, stream)
 
-    log(f"[bench] warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    idg.sync(stream)
-    torch.cuda.synchronize()
-    idg.profile(True)
-    idg.profile_read(reset=True)
-    log(f"[bench] timing {args.steps} steps")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    idg.sync(stream)
-    prof = idg.profile_read(reset=True)
-    idg.profile(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    def timed(steps, warmup):
+        for _ in range(warmup):
+            step()
+        idg.sync(stream)
+        torch.cuda.synchronize()
+        idg.profile(True)
+        idg.profile_read(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        idg.sync(stream)
+        prof = idg.profile_read(reset=True)
+        idg.profile(False)
+        return (t1 - t0) * 1e3 / steps, prof
+
+    tune_info = None
+    if args.form == "auto":
+        from paper_1909_07226_amd.autotune import autotune
+        log("[bench] autotuning the schedule (outside the timed region)")
+        tune_info = autotune(plan, uvw, freqs, vis, aterms, taper, grid, vis_out, use_cache=False, log=log)
+    else:
+        plan.set_tuning(form=args.form, blocks_per_cu=args.blocks_per_cu)
+    if args.adder_chunk:
+        plan.set_tuning(adder_chunk=args.adder_chunk)
+    log(f"[bench] tuning {plan.get_tuning()}; warmup {args.warmup}, timing {args.steps} steps")
+    ms_step, prof = timed(args.steps, args.warmup)
     value = nvis / (ms_step * 1e-3) / 1e6
     k = args.steps
     g_ms, g_n = prof["gridder"]
@@ -170,6 +230,14 @@ def main():
     log(f"[bench] {ms_step:.2f} ms/step, {value:.1f} MVis/s; gridder {g_launch_ms:.3f} ms/launch "
         f"({achieved:.2f} TFLOP/s), adder {a_ms / max(1, a_n):.3f} ms, degridder {d_launch_ms:.3f} ms "
         f"({d_achieved:.2f} TFLOP/s)")
+    tuned = plan.get_tuning()
+    plain_form = None
+    if args.form == "auto":
+        plan.set_tuning(form="plain", blocks_per_cu=0, adder_chunk=tuned["adder_chunk"])
+        p_ms, _ = timed(args.steps, 1)
+        plain_form = {"ms_per_step": round(p_ms, 4), "value": round(nvis / (p_ms * 1e-3) / 1e6, 3)}
+        log(f"[bench] plain form: {plain_form}")
+        plan.set_tuning(**tuned)
 
     result = {
         "metric": "MVis/s grid+degrid, % of FP32 VALU peak; p50/p99 job latency vs plain",
@@ -186,7 +254,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_DESC[args.workload], "nr_visibilities": nvis,
                    "nr_subgrids": st["nr_subgrids"], "subgrid_size": L, "grid_size": N,
-                   "polarisations": 4, "phase_offsets": "f64", "taper": "PSWF beta=7"},
+                   "polarisations": 4, "phase_offsets": "f64", "taper": "PSWF beta=7",
+                   "tuning": tuned},
         "roofline": {"bound": "alu", "kernel": "gridder", "achieved": round(achieved, 3),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                      "traffic": None, "work_per_launch": f"{FLOP_PER_VIS_PIX} flop x {nvis} vis x {L * L} pix",
@@ -198,12 +267,24 @@ def main():
         "degridder_roofline": {"achieved": round(d_achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                                "frac": round(d_achieved / FP32_PEAK_TFLOPS, 4)},
         "plan_ms": round(plan_ms, 1),
+        "plain_form": plain_form,
+        "autotune_ms": tune_info["timings_ms"] if tune_info else None,
         "cpu_baseline": None,
     }
+    if args.serve_jobs > 0 and args.workload == "lofar":
+        result["serving"] = serving_leg(wl, dict(uvw=uvw, freqs=freqs, vis=vis, aterms=aterms, taper=taper),
+                                        args.serve_jobs, log)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline (oracle, ~{args.cpu_budget:.0f} s)")
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
         log(f"[bench] cpu baseline {result['cpu_baseline']}")
+    if args.copy_calibration > 0:
+        src = torch.empty(args.copy_calibration // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {args.copy_calibration} bytes read and written")
     print(json.dumps(result), flush=True)
 
 

@@ -130,6 +130,35 @@ int idg_plan_stats(idg_plan_t plan, int64_t *nr_subgrids, int64_t *nr_gridded, i
  *             grouped by subgrid (rows vis_offset .. vis_offset + nvis - 1), t-major. */
 int idg_plan_export(idg_plan_t plan, int64_t *subgrids, int32_t *samples);
 
+/* Scheduling knobs of a plan (the path's schedule, not its arithmetic: every
+ * setting gives the same result up to float32 summation order in the adder).
+ *   grid_form, degrid_form
+ *                  IDG_FORM_PLAIN: one workgroup per subgrid;
+ *                  IDG_FORM_PERSISTENT: a fixed set of workgroups takes subgrids
+ *                  from a device work queue, costliest (most visibilities)
+ *                  first -- for many small or uneven subgrids;
+ *   grid_blocks_per_cu, degrid_blocks_per_cu
+ *                  persistent form: workgroups per compute unit (0 = as many as fit);
+ *   adder_chunk    adder: the longest run of one grid tile's subgrid list handled
+ *                  by one workgroup; longer lists are summed in parallel chunks
+ *                  whose partial tiles are added in order (0 = 256);
+ *   reserved       must be 0.
+ * idg_plan_set_tuning validates (IDG_EINVAL) and stores the knobs; call it
+ * only when no work queued with the plan is pending.  New plans start with
+ * all fields 0 (plain forms, default chunk). */
+#define IDG_FORM_PLAIN 0
+#define IDG_FORM_PERSISTENT 1
+typedef struct {
+  int32_t grid_form;
+  int32_t degrid_form;
+  int32_t grid_blocks_per_cu;
+  int32_t degrid_blocks_per_cu;
+  int32_t adder_chunk;
+  int32_t reserved[3];
+} idg_tuning;
+int idg_plan_set_tuning(idg_plan_t plan, const idg_tuning *tuning);
+int idg_plan_get_tuning(idg_plan_t plan, idg_tuning *tuning);
+
 /* Release the plan and its device metadata.  Work queued with it must have
  * finished.  NULL is ignored. */
 void idg_plan_destroy(idg_plan_t plan);

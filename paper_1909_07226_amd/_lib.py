@@ -21,7 +21,9 @@ SUBGRID_FIELDS = ("bl", "t0", "nt", "c0", "nc", "x0", "y0", "slot", "s1", "s2", 
 
 EXPORTED = ("idg_plan", "idg_plan_stats", "idg_plan_export", "idg_plan_destroy", "idg_grid", "idg_degrid",
             "idg_grid_subgrids", "idg_subgrid_fft", "idg_add_subgrids", "idg_split_subgrids", "idg_sync",
-            "idg_last_error", "idg_version", "idg_profile", "idg_profile_read")
+            "idg_last_error", "idg_version", "idg_profile", "idg_profile_read", "idg_plan_set_tuning",
+            "idg_plan_get_tuning")
+FORM_PLAIN, FORM_PERSISTENT = 0, 1
 STAGES = ("gridder", "adder", "degridder", "zero")
 
 
@@ -31,6 +33,16 @@ class Params(ctypes.Structure):
                 ("nr_stations", ctypes.c_int32), ("nr_baselines", ctypes.c_int32), ("nr_timesteps", ctypes.c_int32),
                 ("nr_channels", ctypes.c_int32), ("flags", ctypes.c_uint32), ("image_size", ctypes.c_double),
                 ("scratch_bytes", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("grid_form", ctypes.c_int32), ("degrid_form", ctypes.c_int32),
+                ("grid_blocks_per_cu", ctypes.c_int32), ("degrid_blocks_per_cu", ctypes.c_int32),
+                ("adder_chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+_FORMS = {"plain": FORM_PLAIN, "persistent": FORM_PERSISTENT}
+_FORM_NAMES = {v: k for k, v in _FORMS.items()}
 
 
 class IDGError(RuntimeError):
@@ -67,6 +79,8 @@ def lib():
         L.idg_version.argtypes = []
         L.idg_profile.argtypes = [ctypes.c_int]
         L.idg_profile_read.argtypes = [vp, vp, ctypes.c_int]
+        L.idg_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.idg_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         for name in EXPORTED:
             if name not in ("idg_plan_destroy", "idg_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -164,6 +178,29 @@ class Plan:
     @property
     def nr_subgrids(self):
         return self.stats()["nr_subgrids"]
+
+    def set_tuning(self, form=None, blocks_per_cu=None, adder_chunk=None, grid_form=None, degrid_form=None,
+                   grid_blocks_per_cu=None, degrid_blocks_per_cu=None):
+        """Scheduling knobs (idg_plan_set_tuning).  ``form`` / ``blocks_per_cu`` set both directions;
+        the grid_/degrid_ arguments set one.  Unspecified knobs keep their value."""
+        cur = self.get_tuning()
+        gf = grid_form if grid_form is not None else (form if form is not None else cur["grid_form"])
+        df = degrid_form if degrid_form is not None else (form if form is not None else cur["degrid_form"])
+        gb = grid_blocks_per_cu if grid_blocks_per_cu is not None else (
+            blocks_per_cu if blocks_per_cu is not None else cur["grid_blocks_per_cu"])
+        db = degrid_blocks_per_cu if degrid_blocks_per_cu is not None else (
+            blocks_per_cu if blocks_per_cu is not None else cur["degrid_blocks_per_cu"])
+        t = Tuning(_FORMS.get(gf, gf), _FORMS.get(df, df), int(gb), int(db),
+                   cur["adder_chunk"] if adder_chunk is None else int(adder_chunk))
+        check(lib().idg_plan_set_tuning(self._handle, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        check(lib().idg_plan_get_tuning(self._handle, ctypes.byref(t)))
+        return dict(grid_form=_FORM_NAMES.get(t.grid_form, t.grid_form),
+                    degrid_form=_FORM_NAMES.get(t.degrid_form, t.degrid_form),
+                    grid_blocks_per_cu=t.grid_blocks_per_cu, degrid_blocks_per_cu=t.degrid_blocks_per_cu,
+                    adder_chunk=t.adder_chunk)
 
     def export(self):
         """(subgrids int64 [P, 12] with SUBGRID_FIELDS columns, samples int32 [K, 2] of (t, c))."""

@@ -44,26 +44,31 @@ constexpr int64_t kDefaultScratch = int64_t(2) << 30;
 
 // Device-resident plan metadata on one device.
 struct Batch {
-  int64_t first = 0, count = 0;    // plan subgrids [first, first + count)
-  int64_t tile_off = 0, ntiles = 0;  // rows in tile_ids; tile_start rows tile_off + b .. (ntiles + 1 entries)
-  int64_t start_off = 0;
+  int64_t first = 0, count = 0;      // plan subgrids [first, first + count)
+  int64_t order_off = 0;             // gridder work list (local indices, costliest first)
+  int64_t item_off = 0, nitems = 0;  // adder items
+  int64_t combine_off = 0, ncombine = 0;
+  int64_t nslots = 0;                // partial tiles of this batch
 };
 
 struct DevPlan {
   int device = -1;
+  int nr_cus = 1;
   idg::DevSubgrid *subgrids = nullptr;
   uint32_t *samples = nullptr;
   int64_t *unplanned = nullptr;
   float4 *lmn = nullptr;
   float2 *twiddle = nullptr;
-  int32_t *tile_ids = nullptr, *tile_start = nullptr, *contrib = nullptr;
+  int32_t *grid_order = nullptr, *degrid_order = nullptr, *contrib = nullptr;
+  idg::AdderItem *items = nullptr;
+  idg::CombineItem *combine = nullptr;
   std::vector<Batch> batches;
-  int64_t batch_size = 0;
+  int64_t batch_size = 0, max_slots = 0;
 
   ~DevPlan() {
     int cur = -1;
     if (hipGetDevice(&cur) == hipSuccess && cur != device) (void)hipSetDevice(device);
-    void *ptrs[] = {subgrids, samples, unplanned, lmn, twiddle, tile_ids, tile_start, contrib};
+    void *ptrs[] = {subgrids, samples, unplanned, lmn, twiddle, grid_order, degrid_order, contrib, items, combine};
     for (void *p : ptrs)
       if (p) (void)hipFree(p);
     if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
@@ -107,6 +112,35 @@ void build_tile_lists(const std::vector<idg::SubgridRec> &subs, int64_t first, i
     const int64_t t = active[i];
     out.contrib.insert(out.contrib.end(), flat.begin() + off[size_t(t)], flat.begin() + off[size_t(t) + 1]);
     out.tile_start[i + 1] = int32_t(out.contrib.size());
+  }
+}
+
+// Adder work items for one set of tile lists: runs of at most `chunk`
+// contributions; split tiles get partial slots and a combine entry.  Item
+// positions are offset by `contrib_base` (position of the lists in the
+// concatenated contribution array).
+struct AdderPlan {
+  std::vector<idg::AdderItem> items;
+  std::vector<idg::CombineItem> combine;
+  int32_t nslots = 0;
+};
+
+void build_adder_plan(const TileLists &tl, int chunk, int64_t contrib_base, AdderPlan &out) {
+  out = AdderPlan{};
+  for (size_t i = 0; i < tl.tile_ids.size(); ++i) {
+    const int32_t b = tl.tile_start[i], e = tl.tile_start[i + 1];
+    const int32_t tile = tl.tile_ids[i];
+    if (e - b <= chunk) {
+      out.items.push_back({tile, int32_t(contrib_base + b), int32_t(contrib_base + e), -1});
+      continue;
+    }
+    const int32_t n = (e - b + chunk - 1) / chunk;
+    out.combine.push_back({tile, out.nslots, out.nslots + n, 0});
+    for (int32_t j = 0; j < n; ++j) {
+      const int32_t cb = b + j * chunk, ce = std::min(e, cb + chunk);
+      out.items.push_back({tile, int32_t(contrib_base + cb), int32_t(contrib_base + ce), out.nslots + j});
+    }
+    out.nslots += n;
   }
 }
 
@@ -174,6 +208,7 @@ int upload(T **dst, const T *src, size_t n, const char *what) {
 
 struct idg_plan_s {
   idg::HostPlan host;
+  idg_tuning tuning{};
   std::mutex mu;
   std::map<int, std::unique_ptr<DevPlan>> dev;
 };
@@ -243,28 +278,55 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
   if ((rc = upload(&dp->lmn, lmn.data(), lmn.size(), "plan upload (lmn)")) != IDG_OK) return rc;
   if ((rc = upload(&dp->twiddle, tw.data(), tw.size(), "plan upload (twiddle)")) != IDG_OK) return rc;
 
-  // adder tile lists, one set per scratch batch
+  // cost-sorted work lists: gridder per batch (local indices), degridder over the plan
   const int64_t P = int64_t(h.subgrids.size());
+  auto by_cost = [&](std::vector<int32_t> &ids, int64_t first) {
+    std::stable_sort(ids.begin(), ids.end(), [&](int32_t x, int32_t y) {
+      return h.subgrids[size_t(first + x)].nvis > h.subgrids[size_t(first + y)].nvis;
+    });
+  };
+  std::vector<int32_t> degrid_order(static_cast<size_t>(P));
+  for (int64_t i = 0; i < P; ++i) degrid_order[size_t(i)] = int32_t(i);
+  by_cost(degrid_order, 0);
+
+  // per scratch batch: gridder order and adder items over tile lists
   dp->batch_size = batch_size_of(p);
-  std::vector<int32_t> all_ids, all_start, all_contrib;
+  const int chunk = plan->tuning.adder_chunk > 0 ? plan->tuning.adder_chunk : 256;
+  std::vector<int32_t> grid_order, all_contrib;
+  std::vector<idg::AdderItem> all_items;
+  std::vector<idg::CombineItem> all_combine;
   for (int64_t f = 0; f < P; f += dp->batch_size) {
     Batch b;
     b.first = f;
     b.count = std::min(dp->batch_size, P - f);
+    std::vector<int32_t> ord(static_cast<size_t>(b.count));
+    for (int64_t i = 0; i < b.count; ++i) ord[size_t(i)] = int32_t(i);
+    by_cost(ord, f);
+    b.order_off = int64_t(grid_order.size());
+    grid_order.insert(grid_order.end(), ord.begin(), ord.end());
     TileLists tl;
     build_tile_lists(h.subgrids, b.first, b.count, p.grid_size, L, tl);
-    b.tile_off = int64_t(all_ids.size());
-    b.ntiles = int64_t(tl.tile_ids.size());
-    b.start_off = int64_t(all_start.size());
-    const int32_t base = int32_t(all_contrib.size());
-    all_ids.insert(all_ids.end(), tl.tile_ids.begin(), tl.tile_ids.end());
-    for (int32_t v : tl.tile_start) all_start.push_back(base + v);
+    AdderPlan ap;
+    build_adder_plan(tl, chunk, int64_t(all_contrib.size()), ap);
     all_contrib.insert(all_contrib.end(), tl.contrib.begin(), tl.contrib.end());
+    b.item_off = int64_t(all_items.size());
+    b.nitems = int64_t(ap.items.size());
+    b.combine_off = int64_t(all_combine.size());
+    b.ncombine = int64_t(ap.combine.size());
+    b.nslots = ap.nslots;
+    dp->max_slots = std::max<int64_t>(dp->max_slots, ap.nslots);
+    all_items.insert(all_items.end(), ap.items.begin(), ap.items.end());
+    all_combine.insert(all_combine.end(), ap.combine.begin(), ap.combine.end());
     dp->batches.push_back(b);
   }
-  if ((rc = upload(&dp->tile_ids, all_ids.data(), all_ids.size(), "plan upload (tiles)")) != IDG_OK) return rc;
-  if ((rc = upload(&dp->tile_start, all_start.data(), all_start.size(), "plan upload (tiles)")) != IDG_OK) return rc;
+  if ((rc = upload(&dp->grid_order, grid_order.data(), grid_order.size(), "plan upload (order)")) != IDG_OK)
+    return rc;
+  if ((rc = upload(&dp->degrid_order, degrid_order.data(), degrid_order.size(), "plan upload (order)")) != IDG_OK)
+    return rc;
   if ((rc = upload(&dp->contrib, all_contrib.data(), all_contrib.size(), "plan upload (tiles)")) != IDG_OK) return rc;
+  if ((rc = upload(&dp->items, all_items.data(), all_items.size(), "plan upload (adder)")) != IDG_OK) return rc;
+  if ((rc = upload(&dp->combine, all_combine.data(), all_combine.size(), "plan upload (adder)")) != IDG_OK) return rc;
+  HIP_TRY(hipDeviceGetAttribute(&dp->nr_cus, hipDeviceAttributeMultiprocessorCount, device), "CU count");
   *out = dp.get();
   plan->dev.emplace(device, std::move(dp));
   return IDG_OK;
@@ -444,6 +506,32 @@ int idg_grid_subgrids(idg_plan_t plan, const double *uvw_d, const double *freqs_
   return IDG_OK;
 }
 
+// Scratch of one idg_grid call: [queue counter (256 B)][partial tiles][subgrids].
+struct GridScratch {
+  char *base = nullptr;
+  int32_t *counter = nullptr;
+  float2 *partials = nullptr;
+  float2 *subgrids = nullptr;
+};
+
+static int alloc_grid_scratch(int64_t slots, int64_t nsub, int L, hipStream_t s, GridScratch &g) {
+  const size_t part_bytes = size_t(slots) * 4 * idg::kAdderTile * idg::kAdderTile * sizeof(float2);
+  const size_t sub_bytes = size_t(nsub) * 4 * size_t(L) * L * sizeof(float2);
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&g.base), 256 + part_bytes + sub_bytes, s),
+          "scratch allocation");
+  g.counter = reinterpret_cast<int32_t *>(g.base);
+  g.partials = reinterpret_cast<float2 *>(g.base + 256);
+  g.subgrids = reinterpret_cast<float2 *>(g.base + 256 + part_bytes);
+  return IDG_OK;
+}
+
+static int persistent_blocks(const idg_plan_s *plan, const DevPlan *dp, bool degrid) {
+  const int L = plan->host.params.subgrid_size;
+  const int want = degrid ? plan->tuning.degrid_blocks_per_cu : plan->tuning.grid_blocks_per_cu;
+  const int per_cu = want > 0 ? want : idg::persistent_blocks_per_cu(L, degrid);
+  return std::max(1, per_cu * dp->nr_cus);
+}
+
 int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
              const idg_cf32 *aterms_d, const float *taper_d, idg_cf32 *grid_d, void *stream) {
   if (!plan) return fail(IDG_EINVAL, "idg_grid: plan is NULL");
@@ -456,11 +544,11 @@ int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const 
   const idg_params &p = plan->host.params;
   const int L = p.subgrid_size;
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t per = int64_t(4) * L * L;
   const int64_t nb = std::min<int64_t>(dp->batch_size, int64_t(plan->host.subgrids.size()));
-  float2 *scratch = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&scratch), size_t(nb * per) * sizeof(float2), s),
-          "idg_grid: scratch allocation");
+  GridScratch g;
+  if ((rc = alloc_grid_scratch(dp->max_slots, nb, L, s, g)) != IDG_OK) return rc;
+  const bool persistent = plan->tuning.grid_form == IDG_FORM_PERSISTENT;
+  const int nblocks = persistent ? persistent_blocks(plan, dp, false) : 0;
   idg::KernelArgs a;
   fill_kernel_args(plan, dp, a);
   a.uvw = uvw_d;
@@ -468,7 +556,7 @@ int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const 
   a.vis_in = reinterpret_cast<const float2 *>(vis_d);
   a.aterms = reinterpret_cast<const float2 *>(aterms_d);
   a.taper = taper_d;
-  a.subgrids_out = scratch;
+  a.subgrids_out = g.subgrids;
   a.stage = 1;
   hipError_t err = hipSuccess;
   for (const Batch &b : dp->batches) {
@@ -476,18 +564,21 @@ int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const 
     a.count = int32_t(b.count);
     {
       StageTimer tm(IDG_STAGE_GRIDDER, s);
-      err = idg::launch_gridder(L, a, s);
+      err = persistent ? idg::launch_gridder_persistent(L, a, dp->grid_order + b.order_off, g.counter, nblocks, s)
+                       : idg::launch_gridder(L, a, s);
     }
     if (err != hipSuccess) break;
-    idg::AdderArgs ad;
+    idg::AdderArgs ad{};
     ad.subgrids = dp->subgrids;
     ad.first = b.first;
-    ad.tile_ids = dp->tile_ids + b.tile_off;
-    ad.tile_start = dp->tile_start + b.start_off;
+    ad.items = dp->items + b.item_off;
+    ad.combine = dp->combine + b.combine_off;
     ad.contrib = dp->contrib;
-    ad.subgrids_in = scratch;
+    ad.subgrids_in = g.subgrids;
     ad.grid = reinterpret_cast<float2 *>(grid_d);
-    ad.ntiles = int32_t(b.ntiles);
+    ad.partials = g.partials;
+    ad.nitems = int32_t(b.nitems);
+    ad.ncombine = int32_t(b.ncombine);
     ad.ntx = (p.grid_size + idg::kAdderTile - 1) / idg::kAdderTile;
     ad.grid_size = p.grid_size;
     {
@@ -496,7 +587,7 @@ int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const 
     }
     if (err != hipSuccess) break;
   }
-  hipError_t ef = hipFreeAsync(scratch, s);
+  hipError_t ef = hipFreeAsync(g.base, s);
   if (err != hipSuccess) return hip_fail(err, "idg_grid: launch");
   HIP_TRY(ef, "idg_grid: scratch release");
   return IDG_OK;
@@ -527,12 +618,52 @@ int idg_degrid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, cons
   a.aterms = reinterpret_cast<const float2 *>(aterms_d);
   a.taper = taper_d;
   const int64_t P = int64_t(h.subgrids.size());
+  const int L = h.params.subgrid_size;
+  if (plan->tuning.degrid_form == IDG_FORM_PERSISTENT && P > 0) {
+    int32_t *counter = nullptr;
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&counter), 256, s), "idg_degrid: queue counter");
+    a.first = 0;
+    a.count = int32_t(P);
+    hipError_t err;
+    {
+      StageTimer tm(IDG_STAGE_DEGRIDDER, s);
+      err = idg::launch_degridder_persistent(L, a, dp->degrid_order, counter, persistent_blocks(plan, dp, true), s);
+    }
+    hipError_t ef = hipFreeAsync(counter, s);
+    if (err != hipSuccess) return hip_fail(err, "idg_degrid: launch");
+    HIP_TRY(ef, "idg_degrid: counter release");
+    return IDG_OK;
+  }
   for (int64_t f = 0; f < P; f += (int64_t(1) << 30)) {
     a.first = f;
     a.count = int32_t(std::min<int64_t>(P - f, int64_t(1) << 30));
     StageTimer tm(IDG_STAGE_DEGRIDDER, s);
-    HIP_TRY(idg::launch_degridder(h.params.subgrid_size, a, s), "idg_degrid: launch");
+    HIP_TRY(idg::launch_degridder(L, a, s), "idg_degrid: launch");
   }
+  return IDG_OK;
+}
+
+int idg_plan_set_tuning(idg_plan_t plan, const idg_tuning *t) {
+  if (!plan || !t) return fail(IDG_EINVAL, "idg_plan_set_tuning: NULL argument");
+  for (int32_t f : {t->grid_form, t->degrid_form})
+    if (f != IDG_FORM_PLAIN && f != IDG_FORM_PERSISTENT)
+      return fail(IDG_EINVAL, "idg_plan_set_tuning: unknown form %d", f);
+  for (int32_t b : {t->grid_blocks_per_cu, t->degrid_blocks_per_cu})
+    if (b < 0 || b > 64) return fail(IDG_EINVAL, "idg_plan_set_tuning: blocks_per_cu must be in [0, 64]");
+  if (t->adder_chunk < 0) return fail(IDG_EINVAL, "idg_plan_set_tuning: adder_chunk must be >= 0");
+  if (t->reserved[0] || t->reserved[1] || t->reserved[2])
+    return fail(IDG_EINVAL, "idg_plan_set_tuning: reserved must be 0");
+  std::lock_guard<std::mutex> lock(plan->mu);
+  const bool rebuild = t->adder_chunk != plan->tuning.adder_chunk;
+  plan->tuning = *t;
+  if (rebuild) plan->dev.clear();  // adder items depend on the chunk length; rebuilt on next use
+  return IDG_OK;
+}
+
+int idg_plan_get_tuning(idg_plan_t plan, idg_tuning *t) {
+  if (!plan || !t) return fail(IDG_EINVAL, "idg_plan_get_tuning: NULL argument");
+  std::lock_guard<std::mutex> lock(plan->mu);
+  *t = plan->tuning;
   return IDG_OK;
 }
 
@@ -566,31 +697,40 @@ int idg_add_subgrids(idg_plan_t plan, const idg_cf32 *subgrids_d, int64_t first,
   if (rc != IDG_OK) return rc;
   const idg_params &p = h.params;
   TileLists tl;
+  AdderPlan ap;
   try {
     build_tile_lists(h.subgrids, first, count, p.grid_size, p.subgrid_size, tl);
+    build_adder_plan(tl, plan->tuning.adder_chunk > 0 ? plan->tuning.adder_chunk : 256, 0, ap);
   } catch (const std::bad_alloc &) {
     return fail(IDG_ENOMEM, "idg_add_subgrids: out of host memory");
   }
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  int32_t *buf = nullptr;
-  const size_t n_ids = tl.tile_ids.size(), n_start = tl.tile_start.size(), n_con = tl.contrib.size();
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&buf), (n_ids + n_start + n_con) * sizeof(int32_t), s),
+  const size_t b_items = ap.items.size() * sizeof(idg::AdderItem);
+  const size_t b_comb = ap.combine.size() * sizeof(idg::CombineItem);
+  const size_t b_con = tl.contrib.size() * sizeof(int32_t);
+  const size_t b_part = size_t(ap.nslots) * 4 * idg::kAdderTile * idg::kAdderTile * sizeof(float2);
+  auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+  char *buf = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&buf), align(b_items) + align(b_comb) + align(b_con) + b_part + 256,
+                         s),
           "idg_add_subgrids: allocation");
-  hipError_t err = hipMemcpyAsync(buf, tl.tile_ids.data(), n_ids * 4, hipMemcpyHostToDevice, s);
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(buf + n_ids, tl.tile_start.data(), n_start * 4, hipMemcpyHostToDevice, s);
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(buf + n_ids + n_start, tl.contrib.data(), n_con * 4, hipMemcpyHostToDevice, s);
+  char *p_items = buf, *p_comb = p_items + align(b_items), *p_con = p_comb + align(b_comb);
+  char *p_part = p_con + align(b_con);
+  hipError_t err = hipMemcpyAsync(p_items, ap.items.data(), b_items, hipMemcpyHostToDevice, s);
+  if (err == hipSuccess && b_comb) err = hipMemcpyAsync(p_comb, ap.combine.data(), b_comb, hipMemcpyHostToDevice, s);
+  if (err == hipSuccess) err = hipMemcpyAsync(p_con, tl.contrib.data(), b_con, hipMemcpyHostToDevice, s);
   if (err == hipSuccess) {
-    idg::AdderArgs ad;
+    idg::AdderArgs ad{};
     ad.subgrids = dp->subgrids;
     ad.first = first;
-    ad.tile_ids = buf;
-    ad.tile_start = buf + n_ids;
-    ad.contrib = buf + n_ids + n_start;
+    ad.items = reinterpret_cast<const idg::AdderItem *>(p_items);
+    ad.combine = reinterpret_cast<const idg::CombineItem *>(p_comb);
+    ad.contrib = reinterpret_cast<const int32_t *>(p_con);
     ad.subgrids_in = reinterpret_cast<const float2 *>(subgrids_d);
     ad.grid = reinterpret_cast<float2 *>(grid_d);
-    ad.ntiles = int32_t(n_ids);
+    ad.partials = reinterpret_cast<float2 *>(p_part);
+    ad.nitems = int32_t(ap.items.size());
+    ad.ncombine = int32_t(ap.combine.size());
     ad.ntx = (p.grid_size + idg::kAdderTile - 1) / idg::kAdderTile;
     ad.grid_size = p.grid_size;
     err = idg::launch_adder(p.subgrid_size, ad, s);

@@ -45,21 +45,39 @@ struct KernelArgs {
 // Adder tile: TILE x TILE pixels of one polarisation.
 constexpr int kAdderTile = 32;
 
+// A run of one tile's contribution list; slot < 0: add into the grid,
+// slot >= 0: sum into partial tile `slot` (combined afterwards).
+struct AdderItem {
+  int32_t tile, begin, end, slot;
+};
+
+// A tile whose list was split: partial slots [slot_begin, slot_end) in order.
+struct CombineItem {
+  int32_t tile, slot_begin, slot_end, pad;
+};
+
 struct AdderArgs {
   const DevSubgrid *subgrids;  // plan subgrids (device)
   int64_t first;               // plan index of local subgrid 0
-  const int32_t *tile_ids;     // [ntiles] ty * ntx + tx
-  const int32_t *tile_start;   // [ntiles + 1] into contrib
+  const AdderItem *items;      // [nitems]
+  const CombineItem *combine;  // [ncombine]
   const int32_t *contrib;      // local subgrid indices, ascending per tile
   const float2 *subgrids_in;   // [count][4][L*L]
   float2 *grid;                // [4][N][N]
-  int32_t ntiles, ntx, grid_size;
+  float2 *partials;            // [slots][4][TILE*TILE]
+  int32_t nitems, ncombine, ntx, grid_size;
 };
 
 bool supported_subgrid_size(int L);
 
 hipError_t launch_gridder(int L, const KernelArgs &a, hipStream_t s);
 hipError_t launch_degridder(int L, const KernelArgs &a, hipStream_t s);
+// persistent forms: `order` holds a.count items, *queue_head is zeroed by the launcher
+hipError_t launch_gridder_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
+                                     int nblocks, hipStream_t s);
+hipError_t launch_degridder_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
+                                       int nblocks, hipStream_t s);
+int persistent_blocks_per_cu(int L, bool degrid);
 hipError_t launch_adder(int L, const AdderArgs &a, hipStream_t s);
 hipError_t launch_splitter(int L, const DevSubgrid *subgrids, int64_t first, int64_t count, const float2 *grid,
                            int grid_size, float2 *out, hipStream_t s);

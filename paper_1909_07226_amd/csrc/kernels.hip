@@ -261,36 +261,55 @@ __device__ __forceinline__ void lds_centred_dft(float2 *sg, const float2 *tw) {
 }
 
 // ---------------------------------------------------------------------------
-// Gridder: one workgroup per subgrid, PPT pixels per thread.
+// Gridder: PPT pixels per thread.  Plain form: one workgroup per subgrid.
+// Persistent form: a fixed grid of workgroups pulls subgrids from a work
+// queue (a device counter over a cost-sorted list) until the list is empty.
 
+template <int L>
+struct GridderSmem {
+  static constexpr int NT = Cfg<L>::NT;
+  static constexpr int CH = NT < 256 ? NT : 256;  // visibilities staged per round
+  static constexpr int SG_BYTES = SgLayout<L>::SIZE * 8, STAGE_BYTES = CH * 48;
+  static constexpr int RAW = SG_BYTES > STAGE_BYTES ? SG_BYTES : STAGE_BYTES;
+  float4 raw[RAW / 16];  // staged visibilities, then the subgrid (SgLayout<L>)
+  float2 tw[L];
+  int next;              // work-queue item of the persistent form
+};
+
+// Per-thread pixel coordinates (PPT pixels tid + r NT).
+template <int L>
+struct PixelCoords {
+  static constexpr int PPT = L * L / Cfg<L>::NT;
+  float l[PPT], m[PPT], n[PPT];
+  __device__ __forceinline__ void load(const float4 *lmn) {
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      const float4 q = lmn[threadIdx.x + r * Cfg<L>::NT];
+      l[r] = q.x;
+      m[r] = q.y;
+      n[r] = q.z;
+    }
+  }
+};
+
+// Grid plan subgrid a.first + local into a.subgrids_out[local].  Starts and ends
+// with all threads past a barrier-free point; the caller synchronises before
+// reusing shared memory.
 template <int L, bool FP32_PHASE>
-__global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
-  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT;
-  constexpr int CH = NT < 256 ? NT : 256;  // visibilities staged per round
-  constexpr int SG_BYTES = SgLayout<L>::SIZE * 8, STAGE_BYTES = CH * 48;
-  constexpr int RAW = SG_BYTES > STAGE_BYTES ? SG_BYTES : STAGE_BYTES;
-  __shared__ float4 raw[RAW / 16];
-  __shared__ float2 s_tw[L];
-  float4 *s_uvw = raw;                        // [CH]
-  float4 *s_vis = raw + CH;                   // [CH][2]
-  float2 *s_sg = reinterpret_cast<float2 *>(raw);  // SgLayout<L>, after the visibility loop
-
+__device__ __forceinline__ void grid_one(const KernelArgs &a, int local, GridderSmem<L> &sm,
+                                         const PixelCoords<L> &pc) {
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT, CH = GridderSmem<L>::CH;
+  float4 *s_uvw = sm.raw;                        // [CH]
+  float4 *s_vis = sm.raw + CH;                   // [CH][2]
+  float2 *s_sg = reinterpret_cast<float2 *>(sm.raw);
   const int tid = threadIdx.x;
-  const DevSubgrid d = a.subgrids[a.first + blockIdx.x];
-  if (tid < L) s_tw[tid] = a.twiddle[tid];
-
-  float pl[PPT], pm[PPT], pn[PPT], p0[PPT];
+  const DevSubgrid d = a.subgrids[a.first + local];
   const double S = a.image_size;
   const double u0 = double(d.x0 + L / 2 - a.grid_size / 2) / S;
   const double v0 = double(d.y0 + L / 2 - a.grid_size / 2) / S;
+  float p0[PPT];
 #pragma unroll
-  for (int r = 0; r < PPT; ++r) {
-    const float4 q = a.lmn[tid + r * NT];
-    pl[r] = q.x;
-    pm[r] = q.y;
-    pn[r] = q.z;
-    p0[r] = FP32_PHASE ? float(u0) * q.x + float(v0) * q.y : 0.0f;
-  }
+  for (int r = 0; r < PPT; ++r) p0[r] = FP32_PHASE ? float(u0) * pc.l[r] + float(v0) * pc.m[r] : 0.0f;
 
   float2 acc[PPT][4];
 #pragma unroll
@@ -325,7 +344,7 @@ __global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
       const float4 v01 = s_vis[2 * k], v23 = s_vis[2 * k + 1];
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
-        float ph = o.x * pl[r] + o.y * pm[r] + o.z * pn[r];
+        float ph = o.x * pc.l[r] + o.y * pc.m[r] + o.z * pc.n[r];
         if (FP32_PHASE) ph -= p0[r];
         ph = __builtin_amdgcn_fractf(ph);
         const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
@@ -356,13 +375,42 @@ __global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
     for (int pol = 0; pol < 4; ++pol) s_sg[SgLayout<L>::idx(pol, pix)] = acc[r][pol];
   }
   __syncthreads();
-  if (a.stage == 1) lds_centred_dft<L, NT, false>(s_sg, s_tw);
+  if (a.stage == 1) lds_centred_dft<L, NT, false>(s_sg, sm.tw);
 
-  float2 *out = a.subgrids_out + int64_t(blockIdx.x) * 4 * NPIX;
+  float2 *out = a.subgrids_out + int64_t(local) * 4 * NPIX;
 #pragma unroll
   for (int r = 0; r < PPT; ++r)
 #pragma unroll
     for (int pol = 0; pol < 4; ++pol) out[pol * NPIX + tid + r * NT] = s_sg[SgLayout<L>::idx(pol, tid + r * NT)];
+}
+
+template <int L, bool FP32_PHASE>
+__global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
+  __shared__ GridderSmem<L> sm;
+  if (threadIdx.x < L) sm.tw[threadIdx.x] = a.twiddle[threadIdx.x];
+  PixelCoords<L> pc;
+  pc.load(a.lmn);
+  grid_one<L, FP32_PHASE>(a, blockIdx.x, sm, pc);
+}
+
+// Persistent form: items order[0 .. count-1] (local subgrid indices, costliest
+// first) are taken one at a time through the counter *queue_head (zero before
+// the launch).  Every workgroup leaves once the counter passes the end.
+template <int L, bool FP32_PHASE>
+__global__ void __launch_bounds__(Cfg<L>::NT) gridder_persistent_kernel(KernelArgs a, const int32_t *order,
+                                                                       int32_t *queue_head) {
+  __shared__ GridderSmem<L> sm;
+  if (threadIdx.x < L) sm.tw[threadIdx.x] = a.twiddle[threadIdx.x];
+  PixelCoords<L> pc;
+  pc.load(a.lmn);
+  for (;;) {
+    if (threadIdx.x == 0) sm.next = atomicAdd(queue_head, 1);
+    __syncthreads();
+    const int item = sm.next;
+    if (item >= a.count) break;
+    grid_one<L, FP32_PHASE>(a, order[item], sm, pc);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -374,23 +422,27 @@ __global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
 
 constexpr int kDegridPartCap = 512;  // G * K_p limit of the partial-sum buffer (32 bytes each)
 
+// A wave holds 64/Q lane groups of Q lanes; each group works on one task:
+// Q x V visibilities (lane i of the group owns visibilities chunk*Q*V + v*Q + i)
+// over a 1/G share of the pixels.
 template <int L, int V, bool FP32_PHASE>
 __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgrid &d, const float4 *s_b,
-                                             const float4 *s_lmn, float4 *s_part, int G, int nchunks, double u0,
-                                             double v0) {
+                                             const float4 *s_lmn, float4 *s_part, int G, int nchunks, int Q,
+                                             double u0, double v0) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L, W = NT / 64;
   constexpr bool LMN_LDS = L <= 48;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int R = 64 / Q, lq = lane % Q;
   const float u0f = float(u0), v0f = float(v0);
   const int K = d.nvis;
-  for (int task = wave; task < nchunks * G; task += W) {
+  for (int task = wave * R + lane / Q; task < nchunks * G; task += W * R) {
     const int chunk = task / G, g = task % G;
     float du[V], dv[V], w[V];
     int64_t out_idx[V];
     bool valid[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      const int k = (chunk * V + v) * 64 + lane;
+      const int k = (chunk * V + v) * Q + lq;
       valid[v] = k < K;
       du[v] = dv[v] = w[v] = 0.0f;
       out_idx[v] = 0;
@@ -447,7 +499,7 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
         o[0] = r0;
         o[1] = r1;
       } else {
-        const int k = (chunk * V + v) * 64 + lane;
+        const int k = (chunk * V + v) * Q + lq;
         s_part[2 * (g * K + k)] = r0;
         s_part[2 * (g * K + k) + 1] = r1;
       }
@@ -455,18 +507,23 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
   }
 }
 
-template <int L, bool FP32_PHASE>
-__global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
-  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT, W = NT / 64;
-  constexpr bool LMN_LDS = L <= 48;  // at L = 64 the pixel coordinates are read through the cache
-  __shared__ float2 s_sg[SgLayout<L>::SIZE];  // SgLayout<L>, then [NPIX][4] after the A-terms
-  __shared__ float4 s_lmn[LMN_LDS ? NPIX : 1];
-  __shared__ float2 s_tw[L];
-  __shared__ float4 s_part[2 * kDegridPartCap];  // [G][K] partial sums, 4 complex each  // partial sums of pixel shares
+template <int L>
+struct DegridderSmem {
+  static constexpr bool LMN_LDS = L <= 48;  // at L = 64 the pixel coordinates are read through the cache
+  float2 sg[SgLayout<L>::SIZE];             // SgLayout<L>, then [NPIX][4] after the A-terms
+  float4 lmn[LMN_LDS ? L * L : 1];
+  float2 tw[L];
+  float4 part[2 * kDegridPartCap];          // [G][K] partial sums, 4 complex each
+  int next;                                 // work-queue item of the persistent form
+};
 
+// Degrid plan subgrid p (global index) into a.vis_out.  The caller has loaded
+// sm.tw and sm.lmn and synchronises before reusing shared memory.
+template <int L, bool FP32_PHASE>
+__device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, DegridderSmem<L> &sm) {
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT, W = NT / 64;
   const int tid = threadIdx.x;
-  const DevSubgrid d = a.subgrids[a.first + blockIdx.x];
-  if (tid < L) s_tw[tid] = a.twiddle[tid];
+  const DevSubgrid d = a.subgrids[p];
   const int N = a.grid_size;
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
@@ -474,11 +531,10 @@ __global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
     const int row = pix / L, col = pix % L;
 #pragma unroll
     for (int pol = 0; pol < 4; ++pol)
-      s_sg[SgLayout<L>::idx(pol, pix)] = a.grid_in[(int64_t(pol) * N + d.y0 + row) * N + d.x0 + col];
-    if (LMN_LDS) s_lmn[pix] = a.lmn[pix];
+      sm.sg[SgLayout<L>::idx(pol, pix)] = a.grid_in[(int64_t(pol) * N + d.y0 + row) * N + d.x0 + col];
   }
   __syncthreads();
-  lds_centred_dft<L, NT, true>(s_sg, s_tw);
+  lds_centred_dft<L, NT, true>(sm.sg, sm.tw);
 
   const float2 *j1 = a.aterms + int64_t(d.a1) * NPIX * 4;
   const float2 *j2 = a.aterms + int64_t(d.a2) * NPIX * 4;
@@ -491,12 +547,12 @@ __global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
     for (int e = 0; e < 4; ++e) {
       J1[e] = j1[pix * 4 + e];
       J2[e] = j2[pix * 4 + e];
-      b[r][e] = s_sg[SgLayout<L>::idx(e, pix)];
+      b[r][e] = sm.sg[SgLayout<L>::idx(e, pix)];
     }
     apply_aterms_degrid(J1, J2, a.taper[pix], b[r]);
   }
   __syncthreads();
-  float4 *s_b = reinterpret_cast<float4 *>(s_sg);  // [NPIX][2] = 4 complex per pixel
+  float4 *s_b = reinterpret_cast<float4 *>(sm.sg);  // [NPIX][2] = 4 complex per pixel
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
     const int pix = tid + r * NT;
@@ -505,17 +561,20 @@ __global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
   }
   __syncthreads();
 
-  // visibilities per lane V and pixel shares G (a power of two): fill the W waves with tasks first,
-  // then prefer the largest V (fewest LDS reads per visibility)
+  // lane groups of Q lanes (small subgrids use groups of 32 or 16 so that lanes are not idle),
+  // visibilities per lane V and pixel shares G (a power of two): fill the W * 64/Q lane groups
+  // with tasks first, then prefer the largest V (fewest LDS reads per visibility)
   const int K = d.nvis;
-  const int n64 = (K + 63) / 64;
-  int V = 1, G = 1, nchunks = n64, best = -1;
+  const int Q = K >= 64 ? 64 : (K > 16 ? 32 : 16);
+  const int slots = W * (64 / Q);
+  const int nq = (K + Q - 1) / Q;
+  int V = 1, G = 1, nchunks = nq, best = -1;
   for (int vc = 4; vc >= 1; vc /= 2) {
-    if (vc > 1 && n64 < vc) continue;
-    const int nc = (n64 + vc - 1) / vc;
+    if (vc > 1 && nq < vc) continue;
+    const int nc = (nq + vc - 1) / vc;
     int gc = 1;
-    while (2 * gc * nc <= W && 2 * gc * K <= kDegridPartCap && NPIX % (2 * gc) == 0) gc *= 2;
-    const int filled = min(nc * gc, W);
+    while (2 * gc * nc <= slots && 2 * gc * K <= kDegridPartCap && NPIX % (2 * gc) == 0) gc *= 2;
+    const int filled = min(nc * gc, slots);
     if (filled > best) {
       best = filled;
       V = vc;
@@ -527,17 +586,17 @@ __global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
   const double u0 = double(d.x0 + L / 2 - N / 2) / S;
   const double v0 = double(d.y0 + L / 2 - N / 2) / S;
   if (V == 4)
-    degrid_tasks<L, 4, FP32_PHASE>(a, d, s_b, s_lmn, s_part, G, nchunks, u0, v0);
+    degrid_tasks<L, 4, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, Q, u0, v0);
   else if (V == 2)
-    degrid_tasks<L, 2, FP32_PHASE>(a, d, s_b, s_lmn, s_part, G, nchunks, u0, v0);
+    degrid_tasks<L, 2, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, Q, u0, v0);
   else
-    degrid_tasks<L, 1, FP32_PHASE>(a, d, s_b, s_lmn, s_part, G, nchunks, u0, v0);
+    degrid_tasks<L, 1, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, Q, u0, v0);
   if (G > 1) {
     __syncthreads();
     for (int k = tid; k < K; k += NT) {
-      float4 s0 = s_part[2 * k], s1 = s_part[2 * k + 1];
+      float4 s0 = sm.part[2 * k], s1 = sm.part[2 * k + 1];
       for (int g = 1; g < G; ++g) {
-        const float4 p0 = s_part[2 * (g * K + k)], p1 = s_part[2 * (g * K + k) + 1];
+        const float4 p0 = sm.part[2 * (g * K + k)], p1 = sm.part[2 * (g * K + k) + 1];
         s0.x += p0.x; s0.y += p0.y; s0.z += p0.z; s0.w += p0.w;
         s1.x += p1.x; s1.y += p1.y; s1.z += p1.z; s1.w += p1.w;
       }
@@ -550,16 +609,52 @@ __global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
   }
 }
 
+template <int L>
+__device__ __forceinline__ void degrid_load_tables(const KernelArgs &a, DegridderSmem<L> &sm) {
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L;
+  if (threadIdx.x < L) sm.tw[threadIdx.x] = a.twiddle[threadIdx.x];
+  if (DegridderSmem<L>::LMN_LDS)
+    for (int pix = threadIdx.x; pix < NPIX; pix += NT) sm.lmn[pix] = a.lmn[pix];
+}
+
+template <int L, bool FP32_PHASE>
+__global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
+  __shared__ DegridderSmem<L> sm;
+  degrid_load_tables<L>(a, sm);
+  degrid_one<L, FP32_PHASE>(a, a.first + blockIdx.x, sm);
+}
+
+// Persistent form: items order[0 .. count-1] (global subgrid indices, costliest
+// first) through the counter *queue_head (zero before the launch).
+template <int L, bool FP32_PHASE>
+__global__ void __launch_bounds__(Cfg<L>::NT) degridder_persistent_kernel(KernelArgs a, const int32_t *order,
+                                                                         int32_t *queue_head) {
+  __shared__ DegridderSmem<L> sm;
+  degrid_load_tables<L>(a, sm);
+  for (;;) {
+    if (threadIdx.x == 0) sm.next = atomicAdd(queue_head, 1);
+    __syncthreads();
+    const int item = sm.next;
+    if (item >= a.count) break;
+    degrid_one<L, FP32_PHASE>(a, order[item], sm);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Adder: one workgroup per (grid tile, polarisation).  The tile is read once,
-// every subgrid overlapping it is added in plan order, and it is written once.
+// Adder: one workgroup per (work item, polarisation).  A work item is a grid
+// tile with a contiguous run of its contribution list (subgrids overlapping
+// it, in plan order).  A tile with a short list is one item that reads the
+// tile once, adds every subgrid in order and writes it once.  A long list is
+// cut into chunks whose items sum into partial tiles; combine_kernel then adds
+// the partials to the grid in chunk order.  Deterministic, no atomics.
 
 template <int L>
 __global__ void __launch_bounds__(256) adder_kernel(AdderArgs a) {
-  constexpr int T = kAdderTile, ROWS = 256 / T, PER = T / ROWS, NPIX = L * L;
-  const int tile = a.tile_ids[blockIdx.x];
+  constexpr int T = kAdderTile, ROWS = 256 / T, PER = T / ROWS, NPIX = L * L, U = 4;
+  const AdderItem it = a.items[blockIdx.x];
   const int pol = blockIdx.y;
-  const int tx = tile % a.ntx, ty = tile / a.ntx;
+  const int tx = it.tile % a.ntx, ty = it.tile / a.ntx;
   const int N = a.grid_size;
   const int px = threadIdx.x % T, py = threadIdx.x / T;
   const int x = tx * T + px;
@@ -568,30 +663,75 @@ __global__ void __launch_bounds__(256) adder_kernel(AdderArgs a) {
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int y = ty * T + py + k * ROWS;
-    acc[k] = (x < N && y < N) ? gp[int64_t(y) * N + x] : make_float2(0.0f, 0.0f);
+    acc[k] = (it.slot < 0 && x < N && y < N) ? gp[int64_t(y) * N + x] : make_float2(0.0f, 0.0f);
   }
-  const int c_end = a.tile_start[blockIdx.x + 1];
-  for (int c = a.tile_start[blockIdx.x]; c < c_end; ++c) {
-    const int s = a.contrib[c];
-    const DevSubgrid d = a.subgrids[a.first + s];
-    const int ia = x - d.x0;
-    if (ia < 0 || ia >= L) continue;
-    const float2 *sp = a.subgrids_in + (int64_t(s) * 4 + pol) * NPIX;
+  for (int c = it.begin; c < it.end; c += U) {
+    float2 v[U][PER];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int jb = ty * T + py + k * ROWS - d.y0;
-      if (jb >= 0 && jb < L) {
-        const float2 v = sp[jb * L + ia];
-        acc[k].x += v.x;
-        acc[k].y += v.y;
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) v[u][k] = make_float2(0.0f, 0.0f);
+      if (c + u < it.end) {
+        const int s = a.contrib[c + u];
+        const DevSubgrid d = a.subgrids[a.first + s];
+        const int ia = x - d.x0;
+        if (ia >= 0 && ia < L) {
+          const float2 *sp = a.subgrids_in + (int64_t(s) * 4 + pol) * NPIX;
+#pragma unroll
+          for (int k = 0; k < PER; ++k) {
+            const int jb = ty * T + py + k * ROWS - d.y0;
+            if (jb >= 0 && jb < L) v[u][k] = sp[jb * L + ia];
+          }
+        }
       }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        acc[k].x += v[u][k].x;
+        acc[k].y += v[u][k].y;
+      }
   }
+  if (it.slot < 0) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int y = ty * T + py + k * ROWS;
+      if (x < N && y < N) gp[int64_t(y) * N + x] = acc[k];
+    }
+  } else {
+    float2 *pp = a.partials + (int64_t(it.slot) * 4 + pol) * T * T;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) pp[(py + k * ROWS) * T + px] = acc[k];
+  }
+}
+
+// Add the partial tiles of split lists to the grid, in chunk order.
+__global__ void __launch_bounds__(256) combine_kernel(AdderArgs a) {
+  constexpr int T = kAdderTile, ROWS = 256 / T, PER = T / ROWS;
+  const CombineItem it = a.combine[blockIdx.x];
+  const int pol = blockIdx.y;
+  const int tx = it.tile % a.ntx, ty = it.tile / a.ntx;
+  const int N = a.grid_size;
+  const int px = threadIdx.x % T, py = threadIdx.x / T;
+  const int x = tx * T + px;
+  float2 *gp = a.grid + int64_t(pol) * N * N;
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int y = ty * T + py + k * ROWS;
-    if (x < N && y < N) gp[int64_t(y) * N + x] = acc[k];
+    if (x >= N || y >= N) continue;
+    float2 acc = gp[int64_t(y) * N + x];
+    for (int sl = it.slot_begin; sl < it.slot_end; ++sl) {
+      const float2 v = a.partials[(int64_t(sl) * 4 + pol) * T * T + (py + k * ROWS) * T + px];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    gp[int64_t(y) * N + x] = acc;
   }
+}
+
+__global__ void zero_counter_kernel(int32_t *p) {
+  if (threadIdx.x == 0) p[0] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -665,6 +805,21 @@ hipError_t launch_gridder(int L, const KernelArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_gridder_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
+                                     int nblocks, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, queue_head);
+  IDG_DISPATCH_L(L, {
+    if (a.phase_fp32)
+      hipLaunchKernelGGL((gridder_persistent_kernel<LL, true>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a, order,
+                         queue_head);
+    else
+      hipLaunchKernelGGL((gridder_persistent_kernel<LL, false>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a, order,
+                         queue_head);
+  });
+  return hipGetLastError();
+}
+
 hipError_t launch_degridder(int L, const KernelArgs &a, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   IDG_DISPATCH_L(L, {
@@ -676,9 +831,52 @@ hipError_t launch_degridder(int L, const KernelArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_degridder_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
+                                       int nblocks, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, queue_head);
+  IDG_DISPATCH_L(L, {
+    if (a.phase_fp32)
+      hipLaunchKernelGGL((degridder_persistent_kernel<LL, true>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a, order,
+                         queue_head);
+    else
+      hipLaunchKernelGGL((degridder_persistent_kernel<LL, false>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a, order,
+                         queue_head);
+  });
+  return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(int L, bool degrid) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (L) {
+#define IDG_OCC(LL)                                                                                           \
+  case LL:                                                                                                    \
+    e = degrid ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, degridder_persistent_kernel<LL, false>,     \
+                                                              Cfg<LL>::NT, 0)                               \
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gridder_persistent_kernel<LL, false>,     \
+                                                              Cfg<LL>::NT, 0);                              \
+    break;
+    IDG_OCC(8)
+    IDG_OCC(16)
+    IDG_OCC(24)
+    IDG_OCC(32)
+    IDG_OCC(48)
+    IDG_OCC(64)
+#undef IDG_OCC
+    default:
+      break;
+  }
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
 hipError_t launch_adder(int L, const AdderArgs &a, hipStream_t s) {
-  if (a.ntiles <= 0) return hipSuccess;
-  IDG_DISPATCH_L(L, { hipLaunchKernelGGL((adder_kernel<LL>), dim3(a.ntiles, 4), dim3(256), 0, s, a); });
+  if (a.nitems > 0) {
+    IDG_DISPATCH_L(L, { hipLaunchKernelGGL((adder_kernel<LL>), dim3(a.nitems, 4), dim3(256), 0, s, a); });
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (a.ncombine > 0) hipLaunchKernelGGL(combine_kernel, dim3(a.ncombine, 4), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

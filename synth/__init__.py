@@ -15,3 +15,4 @@ from .workloads import (  # noqa: F401
     WORKLOAD_NAMES,
 )
 from .taper import pswf_taper_1d, pswf_taper_2d  # noqa: F401
+from .serving import serving_trace  # noqa: F401

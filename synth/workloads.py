@@ -196,9 +196,10 @@ def _solve_h0_for_wmax(bxyz, nt, dt, dec, f_max, target):
 # workloads
 
 
-def _tiny(seed, with_vis):
+def _tiny(seed, with_vis, nt=32, nch=4):
+    # the defaults are the tiny workload; longer / wider variants keep 10 s steps and 0.25 MHz channels
     rng = np.random.default_rng(seed)
-    nst, nt, dt, nch = 8, 32, 10.0, 4
+    nst, dt = 8, 10.0
     L, N, beta = 24, 512, 7
     cell = ARCMIN
     lat, dec = np.deg2rad(52.9), np.deg2rad(52.0)
@@ -211,7 +212,7 @@ def _tiny(seed, with_vis):
     h = OMEGA_EARTH * dt * np.arange(nt)
     uvw = _uvw_tracks(bxyz, h, dec)
     uvw[..., 2] = 0.0
-    freqs = _channel_centres(150e6, 151e6, nch)
+    freqs = _channel_centres(150e6, 150e6 + 0.25e6 * nch, nch)
     aterms = _identity_aterms(1, nst, L)
     vis = None
     if with_vis:
@@ -298,10 +299,13 @@ def _skalow(seed, with_vis):
 _BUILDERS = {"tiny": (_tiny, 1), "lofar": (_lofar, 2), "skalow": (_skalow, 3), "precision": (_precision, 5)}
 
 
-def make_workload(name, with_vis=True, seed=None):
-    """Build a named workload.  ``seed`` defaults to 1909_07226 + the workload's index."""
+def make_workload(name, with_vis=True, seed=None, **sizes):
+    """Build a named workload.  ``seed`` defaults to 1909_07226 + the workload's index.
+
+    ``tiny`` accepts ``nt`` and ``nch`` to make a longer or wider variant of the same array.
+    """
     fn, idx = _BUILDERS[name]
-    return fn(SEED_BASE + idx if seed is None else seed, with_vis)
+    return fn(SEED_BASE + idx if seed is None else seed, with_vis, **sizes)
 
 
 def subset(wl, baselines=None, nt=None, channels=None):

@@ -137,3 +137,21 @@ def test_empty_plan():
     wl = make_mini(np.zeros((2, 0, 3)), N=64, L=16, beta=3)
     p = idg.Plan.from_workload(wl)
     assert p.stats() == dict(nr_subgrids=0, nr_gridded=0, nr_dropped=0, nr_flagged=0)
+
+
+def test_tuning_round_trip_and_validation():
+    p = idg.Plan(**_mini_params())
+    assert p.get_tuning() == dict(grid_form="plain", degrid_form="plain", grid_blocks_per_cu=0,
+                                  degrid_blocks_per_cu=0, adder_chunk=0)
+    p.set_tuning(form="persistent", blocks_per_cu=3, adder_chunk=17)
+    assert p.get_tuning() == dict(grid_form="persistent", degrid_form="persistent", grid_blocks_per_cu=3,
+                                  degrid_blocks_per_cu=3, adder_chunk=17)
+    p.set_tuning(degrid_form="plain", grid_blocks_per_cu=2)
+    t = p.get_tuning()
+    assert (t["grid_form"], t["degrid_form"], t["grid_blocks_per_cu"], t["degrid_blocks_per_cu"]) == (
+        "persistent", "plain", 2, 3)
+    for bad in (dict(form=7), dict(blocks_per_cu=-1), dict(degrid_blocks_per_cu=65), dict(adder_chunk=-2)):
+        with pytest.raises(idg.IDGError) as e:
+            p.set_tuning(**bad)
+        assert e.value.code == -1
+    assert p.get_tuning()["adder_chunk"] == 17          # unchanged by the rejected calls

@@ -280,6 +280,54 @@ def test_empty_plan_degrid_zeroes(gpu):
     assert torch.count_nonzero(g).item() == 0 and torch.count_nonzero(vis).item() == 0
 
 
+@pytest.mark.parametrize("name", ["tiny", "lofar-subset", "skalow-subset-flags"])
+def test_persistent_form_equals_plain(gpu, name):
+    # the work-queue form runs the same per-subgrid arithmetic: results are bitwise identical
+    torch, idg = gpu
+    wl, oplan = _case(name)
+    say(f"[persistent form] case={name}")
+    d = to_dev(wl)
+    out = {}
+    for form in ("plain", "persistent"):
+        plan = idg.Plan.from_workload(wl, scratch_bytes=4 * 32 * 1024 * 8 * 7)
+        plan.set_tuning(form=form, blocks_per_cu=2 if form == "persistent" else 0)
+        g = _grid_gpu(torch, idg, wl, plan, d)
+        v = torch.empty(tuple(wl.vis.shape), dtype=torch.complex64, device="cuda")
+        idg.degrid(plan, d["uvw"], d["freqs"], g, d["aterms"], d["taper"], v)
+        idg.sync()
+        out[form] = (g, v)
+    assert torch.equal(out["plain"][0], out["persistent"][0])
+    assert torch.equal(out["plain"][1], out["persistent"][1])
+
+
+def test_adder_chunks_split_long_tile_lists(gpu):
+    # a tiny chunk length splits every tile list: still deterministic and equal to the oracle
+    torch, idg = gpu
+    wl, oplan = _case("lofar-subset")
+    say("[adder chunks]")
+    d = to_dev(wl)
+    plan = idg.Plan.from_workload(wl)
+    plan.set_tuning(adder_chunk=2)
+    a = _grid_gpu(torch, idg, wl, plan, d)
+    b = _grid_gpu(torch, idg, wl, plan, d)
+    assert torch.equal(a, b)
+    ref = oidg.grid(oplan, wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)
+    assert rms_rel(a.cpu().numpy(), ref) < GRID_RMS_TOL
+    # the standalone adder with split lists against the same float32 additions (tolerance: order differs)
+    N, L = wl.grid_size, wl.subgrid_size
+    P = oplan.nr_subgrids
+    rng = np.random.default_rng(9)
+    sub = (rng.standard_normal((P, 4, L, L)) + 1j * rng.standard_normal((P, 4, L, L))).astype(np.complex64)
+    g = torch.zeros((4, N, N), dtype=torch.complex64, device="cuda")
+    idg.add_subgrids(plan, torch.from_numpy(sub).cuda(), 0, g)
+    idg.sync()
+    ref = np.zeros((4, N, N), np.complex128)
+    for p in range(P):
+        x0, y0 = oplan.subgrids[p, F["x0"]], oplan.subgrids[p, F["y0"]]
+        ref[:, y0:y0 + L, x0:x0 + L] += sub[p]
+    assert max_rel(g.cpu().numpy(), ref) < 1e-6
+
+
 # ---------------------------------------------------------------------------
 # full-size LOFAR-like workload (the benchmark configuration)
 
