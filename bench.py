@@ -18,8 +18,10 @@ sample, timed on this host.
 """
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -34,6 +36,39 @@ WORKLOAD_DESC = {
     "skalow": "skalow-like share: 512 stations (130816 baselines), 64 x 1 s, 16 ch 50-350 MHz, L=32, "
               "8192^2 grid at 1 arcsec, A-terms every 32 timesteps, 10% flags",
 }
+
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1909_07226_amd", "csrc", "kernels.hip")
+HBM_RECORD = os.path.join(ROOT, "profiles", "lofar_hbm_counters.md")
+
+
+def kernel_source_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def gridder_traffic(workload, form):
+    """HBM bytes per gridder launch from the committed counter summary.
+
+    The summary's ``traffic-record:`` line holds FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch) of the gridder and the factors that map each counter onto
+    the bytes of a plain elementwise kernel of known size.  Returns None when
+    there is no record for this workload and schedule, or when the kernel
+    source has changed since the counters were taken.
+    """
+    try:
+        with open(HBM_RECORD) as f:
+            m = re.search(r"^traffic-record: (.*)$", f.read(), re.M)
+    except OSError:
+        return None
+    if not m:
+        return None
+    rec = dict(kv.split("=", 1) for kv in m.group(1).split())
+    if rec.get("workload") != workload or rec.get("form") != form or rec.get("kernels_sha256") != kernel_source_hash():
+        return None
+    return int(round(float(rec["fetch_kib"]) * 1024 * float(rec["fetch_factor"])
+                     + float(rec["write_kib"]) * 1024 * float(rec["write_factor"])))
 
 
 def log(*a):
@@ -146,6 +181,8 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent form: workgroups per CU (0 = max)")
     ap.add_argument("--adder-chunk", type=int, default=0, help="adder: longest tile-list run per workgroup (0 = 256)")
     ap.add_argument("--serve-jobs", type=int, default=400, help="jobs in the serving trace (0 = skip serving)")
+    ap.add_argument("--scratch-gb", type=float, default=0.0,
+                    help="subgrid scratch budget in GB (0 = enough for the whole plan: one gridder launch)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="finish with a plain device copy of BYTES (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -166,6 +203,11 @@ def main():
     t = time.perf_counter()
     plan = idg.Plan.from_workload(wl)
     plan_ms = (time.perf_counter() - t) * 1e3
+    nsub = plan.stats()["nr_subgrids"]
+    scratch = int(args.scratch_gb * 1e9) if args.scratch_gb > 0 else nsub * 4 * wl.subgrid_size ** 2 * 8 + (1 << 20)
+    if scratch != 2 << 30:
+        # the scratch budget is a plan parameter: re-plan with it (planning time is the first plan's)
+        plan = idg.Plan.from_workload(wl, scratch_bytes=scratch)
     st = plan.stats()
     nvis = st["nr_gridded"]
     L, N = wl.subgrid_size, wl.grid_size
@@ -255,10 +297,13 @@ def main():
         "config": {"workload": WORKLOAD_DESC[args.workload], "nr_visibilities": nvis,
                    "nr_subgrids": st["nr_subgrids"], "subgrid_size": L, "grid_size": N,
                    "polarisations": 4, "phase_offsets": "f64", "taper": "PSWF beta=7",
+                   "scratch_bytes": scratch,
                    "tuning": tuned},
         "roofline": {"bound": "alu", "kernel": "gridder", "achieved": round(achieved, 3),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                     "traffic": None, "work_per_launch": f"{FLOP_PER_VIS_PIX} flop x {nvis} vis x {L * L} pix",
+                     "traffic": gridder_traffic(args.workload, tuned["grid_form"]), "traffic_unit": "bytes/launch",
+                     "kernels_sha256": kernel_source_hash(),
+                     "work_per_launch": f"{FLOP_PER_VIS_PIX} flop x {nvis} vis x {L * L} pix",
                      "avg_launch_ms": round(g_launch_ms, 4)},
         "grid_mvis_s": round(nvis / (grid_ms * 1e-3) / 1e6, 3),
         "degrid_mvis_s": round(nvis / (degrid_ms * 1e-3) / 1e6, 3),
@@ -283,7 +328,7 @@ def main():
         src = torch.empty(args.copy_calibration // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        torch.mul(src, 1.0, out=dst)
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: {args.copy_calibration} bytes read and written")
     print(json.dumps(result), flush=True)

@@ -86,7 +86,10 @@ typedef struct {
   int32_t nr_channels;     /* 0 .. 65535 */
   uint32_t flags;          /* IDG_STRICT | IDG_PHASE_FP32 */
   double image_size;       /* S = N * cell, direction-cosine units (> 0) */
-  int64_t scratch_bytes;   /* device budget for transformed subgrids during idg_grid; 0 = 2 GiB */
+  int64_t scratch_bytes;   /* device budget for transformed subgrids during idg_grid; 0 = 2 GiB.
+                              A budget that holds every subgrid of the plan grids it in one launch.
+                              The scratch comes from the device's default stream-ordered memory pool,
+                              whose release threshold the library raises so freed scratch is reused. */
 } idg_params;
 
 /*

@@ -327,6 +327,14 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
   if ((rc = upload(&dp->items, all_items.data(), all_items.size(), "plan upload (adder)")) != IDG_OK) return rc;
   if ((rc = upload(&dp->combine, all_combine.data(), all_combine.size(), "plan upload (adder)")) != IDG_OK) return rc;
   HIP_TRY(hipDeviceGetAttribute(&dp->nr_cus, hipDeviceAttributeMultiprocessorCount, device), "CU count");
+  // idg_grid takes its scratch from the device's stream-ordered pool on every call; keep freed
+  // blocks in the pool (do not return them to the driver at each synchronisation) so that
+  // repeated calls do not remap tens of GB
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
   *out = dp.get();
   plan->dev.emplace(device, std::move(dp));
   return IDG_OK;
@@ -469,6 +477,7 @@ static void fill_kernel_args(const idg_plan_s *plan, const DevPlan *dp, idg::Ker
   a.grid_size = p.grid_size;
   a.image_size = p.image_size;
   a.phase_fp32 = (p.flags & IDG_PHASE_FP32) ? 1 : 0;
+  a.chan_recur = plan->host.uniform_channels ? 1 : 0;
 }
 
 int idg_grid_subgrids(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,

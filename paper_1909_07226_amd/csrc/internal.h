@@ -40,6 +40,7 @@ struct KernelArgs {
   double image_size;
   int32_t stage;       // gridder: 0 = image after A-terms and taper, 1 = after the DFT
   int32_t phase_fp32;  // 1: subgrid offsets in float32 (precision study)
+  int32_t chan_recur;  // 1: channel frequencies are uniformly spaced (phasor recurrence over channels)
 };
 
 // Adder tile: TILE x TILE pixels of one polarisation.

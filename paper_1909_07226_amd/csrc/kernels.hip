@@ -8,10 +8,14 @@
 //   degridder  splitter, inverse centred DFT, A-terms x taper, and the
 //              per-visibility sum over pixels (Algorithm 2)
 //
-// The phasor sum is not a dense contraction (each term needs its own
-// sin/cos), so it runs on the VALU: float32 phase per (visibility, pixel)
-// from float64 per-subgrid offsets, v_sin_f32 / v_cos_f32 on the phase in
-// revolutions, and float32 multiply-adds.
+// The phasor sum is not a dense contraction (each term has its own phasor), so
+// it runs on the VALU: float32 phase per (visibility, pixel) from float64
+// per-subgrid offsets, v_sin_f32 / v_cos_f32 on the phase in revolutions, and
+// float32 multiply-adds.  When the channel frequencies are evenly spaced, the
+// phase is linear in the channel index (u_k = uvw f / c0), so the phasors of a
+// run of consecutive channels of one timestep are the run's first phasor times
+// powers of one step phasor: one complex multiply per sample replaces sin, cos
+// and the phase arithmetic.
 #include "internal.h"
 
 #include <algorithm>
@@ -265,13 +269,17 @@ __device__ __forceinline__ void lds_centred_dft(float2 *sg, const float2 *tw) {
 // Persistent form: a fixed grid of workgroups pulls subgrids from a work
 // queue (a device counter over a cost-sorted list) until the list is empty.
 
+// Longest run of channels whose phasors are advanced by multiplication with a
+// per-run step phasor instead of evaluating sin and cos per sample.
+constexpr int kChanRun = 16;
+
 template <int L>
 struct GridderSmem {
   static constexpr int NT = Cfg<L>::NT;
   static constexpr int CH = NT < 256 ? NT : 256;  // visibilities staged per round
-  static constexpr int SG_BYTES = SgLayout<L>::SIZE * 8, STAGE_BYTES = CH * 48;
+  static constexpr int SG_BYTES = SgLayout<L>::SIZE * 8, STAGE_BYTES = CH * 64;
   static constexpr int RAW = SG_BYTES > STAGE_BYTES ? SG_BYTES : STAGE_BYTES;
-  float4 raw[RAW / 16];  // staged visibilities, then the subgrid (SgLayout<L>)
+  float4 raw[RAW / 16];  // staged samples (offsets, channel steps, visibilities), then the subgrid
   float2 tw[L];
   int next;              // work-queue item of the persistent form
 };
@@ -292,6 +300,20 @@ struct PixelCoords {
   }
 };
 
+// acc[r] += visibility * phasor[r] for the four polarisations, two fused
+// multiply-adds per real output.
+template <int PPT>
+__device__ __forceinline__ void grid_accumulate(float2 (&acc)[PPT][4], const float2 (&ph)[PPT], float4 v01,
+                                                float4 v23) {
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    cmac(acc[r][0], v01.x, v01.y, ph[r].x, ph[r].y);
+    cmac(acc[r][1], v01.z, v01.w, ph[r].x, ph[r].y);
+    cmac(acc[r][2], v23.x, v23.y, ph[r].x, ph[r].y);
+    cmac(acc[r][3], v23.z, v23.w, ph[r].x, ph[r].y);
+  }
+}
+
 // Grid plan subgrid a.first + local into a.subgrids_out[local].  Starts and ends
 // with all threads past a barrier-free point; the caller synchronises before
 // reusing shared memory.
@@ -299,8 +321,9 @@ template <int L, bool FP32_PHASE>
 __device__ __forceinline__ void grid_one(const KernelArgs &a, int local, GridderSmem<L> &sm,
                                          const PixelCoords<L> &pc) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT, CH = GridderSmem<L>::CH;
-  float4 *s_uvw = sm.raw;                        // [CH]
-  float4 *s_vis = sm.raw + CH;                   // [CH][2]
+  float4 *s_uvw = sm.raw;                        // [CH] offsets (x, y, z) and run length (w)
+  float4 *s_step = sm.raw + CH;                  // [CH] channel steps of run starts
+  float4 *s_vis = sm.raw + 2 * CH;               // [CH][2]
   float2 *s_sg = reinterpret_cast<float2 *>(sm.raw);
   const int tid = threadIdx.x;
   const DevSubgrid d = a.subgrids[a.first + local];
@@ -310,50 +333,91 @@ __device__ __forceinline__ void grid_one(const KernelArgs &a, int local, Gridder
   float p0[PPT];
 #pragma unroll
   for (int r = 0; r < PPT; ++r) p0[r] = FP32_PHASE ? float(u0) * pc.l[r] + float(v0) * pc.m[r] : 0.0f;
+  const bool recur = !FP32_PHASE && a.chan_recur != 0;
 
   float2 acc[PPT][4];
+  float2 ph[PPT], st[PPT];  // current phasor and channel-step phasor per pixel
 #pragma unroll
-  for (int r = 0; r < PPT; ++r)
+  for (int r = 0; r < PPT; ++r) {
+    ph[r] = st[r] = make_float2(1.0f, 0.0f);
 #pragma unroll
     for (int pol = 0; pol < 4; ++pol) acc[r][pol] = make_float2(0.0f, 0.0f);
+  }
 
   for (int k0 = 0; k0 < d.nvis; k0 += CH) {
     const int nk = min(CH, d.nvis - k0);
     if (tid < nk) {
-      const uint32_t pk = a.samples[d.vis_offset + k0 + tid];
-      const int t = d.t0 + int(pk >> 16), c = d.c0 + int(pk & 0xffffu);
+      const uint32_t *smp = a.samples + d.vis_offset + k0;
+      const uint32_t pk = smp[tid];
+      const int dc = int(pk & 0xffffu);
+      const int t = d.t0 + int(pk >> 16), c = d.c0 + dc;
       const int64_t bt = int64_t(d.bl) * a.nr_timesteps + t;
       const double *q = a.uvw + bt * 3;
       const double s = a.freqs[c] / kC0;
+      // Runs: a sample starts a run unless it is the next channel, in the same timestep, of the
+      // sample before it.  A run's phasors after the first are the first times powers of one step
+      // phasor.  Runs stop at staging chunk ends and every kChanRun channels, which bounds the
+      // error of the recurrence.  Run starts store the run length; other samples store 0.
+      int len = 0;
+      const bool cont_prev = recur && tid > 0 && smp[tid - 1] == pk - 1u && dc % kChanRun != 0;
+      if (!cont_prev) {
+        len = 1;
+        if (recur)
+          while (tid + len < nk && smp[tid + len] == pk + uint32_t(len) && (dc + len) % kChanRun != 0) ++len;
+      }
       float4 o;
       if (FP32_PHASE) {
         const float sf = float(s);
-        o = make_float4(float(q[0]) * sf, float(q[1]) * sf, float(q[2]) * sf, 0.0f);
+        o = make_float4(float(q[0]) * sf, float(q[1]) * sf, float(q[2]) * sf, __int_as_float(len));
       } else {
-        o = make_float4(float(q[0] * s - u0), float(q[1] * s - v0), float(q[2] * s), 0.0f);
+        o = make_float4(float(q[0] * s - u0), float(q[1] * s - v0), float(q[2] * s), __int_as_float(len));
       }
       s_uvw[tid] = o;
+      if (len > 1) {
+        const double ds = (a.freqs[c + 1] - a.freqs[c]) / kC0;
+        s_step[tid] = make_float4(float(q[0] * ds), float(q[1] * ds), float(q[2] * ds), 0.0f);
+      }
       const float4 *vp = reinterpret_cast<const float4 *>(a.vis_in + (bt * a.nr_channels + c) * 4);
       s_vis[2 * tid] = vp[0];
       s_vis[2 * tid + 1] = vp[1];
     }
     __syncthreads();
-#pragma unroll 2
-    for (int k = 0; k < nk; ++k) {
+    for (int k = 0; k < nk;) {
       const float4 o = s_uvw[k];
-      const float4 v01 = s_vis[2 * k], v23 = s_vis[2 * k + 1];
+      const int len = __builtin_amdgcn_readfirstlane(__float_as_int(o.w));
 #pragma unroll
       for (int r = 0; r < PPT; ++r) {
-        float ph = o.x * pc.l[r] + o.y * pc.m[r] + o.z * pc.n[r];
-        if (FP32_PHASE) ph -= p0[r];
-        ph = __builtin_amdgcn_fractf(ph);
-        const float sn = __builtin_amdgcn_sinf(ph), cs = __builtin_amdgcn_cosf(ph);
-        // acc += vis * (cs + i sn), two fused multiply-adds per real output
-        cmac(acc[r][0], v01.x, v01.y, cs, sn);
-        cmac(acc[r][1], v01.z, v01.w, cs, sn);
-        cmac(acc[r][2], v23.x, v23.y, cs, sn);
-        cmac(acc[r][3], v23.z, v23.w, cs, sn);
+        float f = o.x * pc.l[r] + o.y * pc.m[r] + o.z * pc.n[r];
+        if (FP32_PHASE) f -= p0[r];
+        f = __builtin_amdgcn_fractf(f);
+        ph[r] = make_float2(__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f));
       }
+      grid_accumulate<PPT>(acc, ph, s_vis[2 * k], s_vis[2 * k + 1]);
+      if (len > 1) {
+        const float4 q = s_step[k];
+#pragma unroll
+        for (int r = 0; r < PPT; ++r) {
+          const float f = __builtin_amdgcn_fractf(q.x * pc.l[r] + q.y * pc.m[r] + q.z * pc.n[r]);
+          st[r] = make_float2(__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f));
+        }
+        // two channels per trip, alternating between two phasor registers
+        int j = 1;
+        for (; j + 1 < len; j += 2) {
+          float2 pa[PPT];
+#pragma unroll
+          for (int r = 0; r < PPT; ++r) pa[r] = cmul(ph[r], st[r]);
+          grid_accumulate<PPT>(acc, pa, s_vis[2 * (k + j)], s_vis[2 * (k + j) + 1]);
+#pragma unroll
+          for (int r = 0; r < PPT; ++r) ph[r] = cmul(pa[r], st[r]);
+          grid_accumulate<PPT>(acc, ph, s_vis[2 * (k + j + 1)], s_vis[2 * (k + j + 1) + 1]);
+        }
+        if (j < len) {
+#pragma unroll
+          for (int r = 0; r < PPT; ++r) ph[r] = cmul(ph[r], st[r]);
+          grid_accumulate<PPT>(acc, ph, s_vis[2 * (k + j)], s_vis[2 * (k + j) + 1]);
+        }
+      }
+      k += len > 1 ? len : 1;
     }
     __syncthreads();
   }
@@ -420,61 +484,47 @@ __global__ void __launch_bounds__(Cfg<L>::NT) gridder_persistent_kernel(KernelAr
 // LDS read of a pixel is used V times.  Pixel shares of one visibility are
 // added in LDS at the end.  V and G are chosen per subgrid to fill the waves.
 
-constexpr int kDegridPartCap = 512;  // G * K_p limit of the partial-sum buffer (32 bytes each)
+constexpr int kDegridPartCap = 192;  // G * K_p limit of the partial-sum buffer (32 bytes each)
 
-// A wave holds 64/Q lane groups of Q lanes; each group works on one task:
-// Q x V visibilities (lane i of the group owns visibilities chunk*Q*V + v*Q + i)
-// over a 1/G share of the pixels.
-template <int L, int V, bool FP32_PHASE>
-__device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgrid &d, const float4 *s_b,
-                                             const float4 *s_lmn, float4 *s_part, int G, int nchunks, int Q,
-                                             double u0, double v0) {
-  constexpr int NT = Cfg<L>::NT, NPIX = L * L, W = NT / 64;
-  constexpr bool LMN_LDS = L <= 48;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int R = 64 / Q, lq = lane % Q;
-  const float u0f = float(u0), v0f = float(v0);
-  const int K = d.nvis;
-  for (int task = wave * R + lane / Q; task < nchunks * G; task += W * R) {
-    const int chunk = task / G, g = task % G;
-    float du[V], dv[V], w[V];
-    int64_t out_idx[V];
-    bool valid[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const int k = (chunk * V + v) * Q + lq;
-      valid[v] = k < K;
-      du[v] = dv[v] = w[v] = 0.0f;
-      out_idx[v] = 0;
-      if (valid[v]) {
-        const uint32_t pk = a.samples[d.vis_offset + k];
-        const int t = d.t0 + int(pk >> 16), c = d.c0 + int(pk & 0xffffu);
-        const int64_t bt = int64_t(d.bl) * a.nr_timesteps + t;
-        const double *q = a.uvw + bt * 3;
-        const double s = a.freqs[c] / kC0;
-        if (FP32_PHASE) {
-          const float sf = float(s);
-          du[v] = float(q[0]) * sf;
-          dv[v] = float(q[1]) * sf;
-          w[v] = float(q[2]) * sf;
-        } else {
-          du[v] = float(q[0] * s - u0);
-          dv[v] = float(q[1] * s - v0);
-          w[v] = float(q[2] * s);
-        }
-        out_idx[v] = (bt * a.nr_channels + c) * 4;
-      }
-    }
-    float2 y[V][4];
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-#pragma unroll
-      for (int pol = 0; pol < 4; ++pol) y[v][pol] = make_float2(0.0f, 0.0f);
-    const int lo = g * (NPIX / G), hi = lo + NPIX / G;
+template <int L>
+struct DegridderSmem {
+  static constexpr bool LMN_LDS = L <= 24;  // larger subgrids read the pixel coordinates through the cache
+  float2 sg[SgLayout<L>::SIZE];             // SgLayout<L>, then [NPIX][4] after the A-terms
+  float4 lmn[LMN_LDS ? L * L : 1];
+  float2 tw[L];
+  float4 part[2 * kDegridPartCap];          // [G][K] partial sums, 4 complex each
+  int next;                                 // work-queue item of the persistent form
+};
+
+// Sum over the pixel share [lo, hi) for a lane's V visibilities.  RECUR: the V
+// visibilities are consecutive channels of one timestep, and the phasor of
+// visibility v is the phasor of visibility 0 times the v-th power of the
+// channel-step phasor (offsets du, dv, w of visibility 0; step sx, sy, sz).
+template <int L, int V, bool FP32_PHASE, bool RECUR>
+__device__ __forceinline__ void degrid_pixels(float2 (&y)[V][4], const float (&du)[V], const float (&dv)[V],
+                                              const float (&w)[V], float sx, float sy, float sz,
+                                              const KernelArgs &a, const float4 *s_b, const float4 *s_lmn,
+                                              int lo, int hi, float u0f, float v0f) {
+  constexpr bool LMN_LDS = DegridderSmem<L>::LMN_LDS;
 #pragma unroll 2
-    for (int pix = lo; pix < hi; ++pix) {
-      const float4 q = LMN_LDS ? s_lmn[pix] : a.lmn[pix];
-      const float4 b01 = s_b[2 * pix], b23 = s_b[2 * pix + 1];
+  for (int pix = lo; pix < hi; ++pix) {
+    const float4 q = LMN_LDS ? s_lmn[pix] : a.lmn[pix];
+    const float4 b01 = s_b[2 * pix], b23 = s_b[2 * pix + 1];
+    if (RECUR) {
+      // y += B * exp(-i phase): with E = exp(+i phase), add B * conj(E)
+      const float f0 = __builtin_amdgcn_fractf(du[0] * q.x + dv[0] * q.y + w[0] * q.z);
+      const float fs = __builtin_amdgcn_fractf(sx * q.x + sy * q.y + sz * q.z);
+      float2 e = make_float2(__builtin_amdgcn_cosf(f0), __builtin_amdgcn_sinf(f0));
+      const float2 st = make_float2(__builtin_amdgcn_cosf(fs), __builtin_amdgcn_sinf(fs));
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        if (v > 0) e = cmul(e, st);
+        cmac(y[v][0], b01.x, b01.y, e.x, -e.y);
+        cmac(y[v][1], b01.z, b01.w, e.x, -e.y);
+        cmac(y[v][2], b23.x, b23.y, e.x, -e.y);
+        cmac(y[v][3], b23.z, b23.w, e.x, -e.y);
+      }
+    } else {
       const float off = FP32_PHASE ? u0f * q.x + v0f * q.y : 0.0f;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
@@ -489,6 +539,75 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
         cmac(y[v][3], b23.z, b23.w, cs, -sn);
       }
     }
+  }
+}
+
+// A wave holds 64/Q lane groups of Q lanes; each group works on one task:
+// Q x V visibilities (lane i of the group owns the V consecutive samples
+// (chunk * Q + i) * V + v) over a 1/G share of the pixels.
+template <int L, int V, bool FP32_PHASE>
+__device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgrid &d, const float4 *s_b,
+                                             const float4 *s_lmn, float4 *s_part, int G, int nchunks, int Q,
+                                             double u0, double v0) {
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L, W = NT / 64;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int R = 64 / Q, lq = lane % Q;
+  const float u0f = float(u0), v0f = float(v0);
+  const int K = d.nvis;
+  const bool recur = !FP32_PHASE && V > 1 && a.chan_recur != 0;
+  for (int task = wave * R + lane / Q; task < nchunks * G; task += W * R) {
+    const int chunk = task / G, g = task % G;
+    const int kbase = (chunk * Q + lq) * V;
+    float du[V], dv[V], w[V];
+    int64_t out_idx[V];
+    bool valid[V];
+    uint32_t pk0 = 0;
+    bool run = recur;  // this lane's valid samples are consecutive channels of one timestep
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int k = kbase + v;
+      valid[v] = k < K;
+      du[v] = dv[v] = w[v] = 0.0f;
+      out_idx[v] = 0;
+      if (valid[v]) {
+        const uint32_t pk = a.samples[d.vis_offset + k];
+        if (v == 0) pk0 = pk;
+        else run = run && pk == pk0 + uint32_t(v);
+        const int t = d.t0 + int(pk >> 16), c = d.c0 + int(pk & 0xffffu);
+        const int64_t bt = int64_t(d.bl) * a.nr_timesteps + t;
+        const double *q = a.uvw + bt * 3;
+        const double s = a.freqs[c] / kC0;
+        if (FP32_PHASE) {
+          const float sf = float(s);
+          du[v] = float(q[0]) * sf;
+          dv[v] = float(q[1]) * sf;
+          w[v] = float(q[2]) * sf;
+        } else {
+          du[v] = float(q[0] * s - u0);
+          dv[v] = float(q[1] * s - v0);
+          w[v] = float(q[2] * s);
+        }
+        if (v == 1 && run) {  // channel c - 1 is sample 0's
+          const double ds = (a.freqs[c] - a.freqs[c - 1]) / kC0;
+          sx = float(q[0] * ds);
+          sy = float(q[1] * ds);
+          sz = float(q[2] * ds);
+        }
+        out_idx[v] = (bt * a.nr_channels + c) * 4;
+      }
+    }
+    float2 y[V][4];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int pol = 0; pol < 4; ++pol) y[v][pol] = make_float2(0.0f, 0.0f);
+    const int lo = g * (NPIX / G), hi = lo + NPIX / G;
+    // the recurrence is taken when every active lane of the wave has a run (a uniform branch)
+    if (__all(run))
+      degrid_pixels<L, V, FP32_PHASE, true>(y, du, dv, w, sx, sy, sz, a, s_b, s_lmn, lo, hi, u0f, v0f);
+    else
+      degrid_pixels<L, V, FP32_PHASE, false>(y, du, dv, w, sx, sy, sz, a, s_b, s_lmn, lo, hi, u0f, v0f);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       if (!valid[v]) continue;
@@ -499,7 +618,7 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
         o[0] = r0;
         o[1] = r1;
       } else {
-        const int k = (chunk * V + v) * Q + lq;
+        const int k = kbase + v;
         s_part[2 * (g * K + k)] = r0;
         s_part[2 * (g * K + k) + 1] = r1;
       }
@@ -507,15 +626,6 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
   }
 }
 
-template <int L>
-struct DegridderSmem {
-  static constexpr bool LMN_LDS = L <= 48;  // at L = 64 the pixel coordinates are read through the cache
-  float2 sg[SgLayout<L>::SIZE];             // SgLayout<L>, then [NPIX][4] after the A-terms
-  float4 lmn[LMN_LDS ? L * L : 1];
-  float2 tw[L];
-  float4 part[2 * kDegridPartCap];          // [G][K] partial sums, 4 complex each
-  int next;                                 // work-queue item of the persistent form
-};
 
 // Degrid plan subgrid p (global index) into a.vis_out.  The caller has loaded
 // sm.tw and sm.lmn and synchronises before reusing shared memory.

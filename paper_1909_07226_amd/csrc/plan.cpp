@@ -211,11 +211,21 @@ class Planner {
 
 }  // namespace
 
+bool uniform_spacing(const double *freqs, int nr_channels) {
+  if (nr_channels < 2) return false;
+  const double d0 = freqs[1] - freqs[0];
+  if (!(d0 > 0.0)) return false;
+  for (int c = 1; c + 1 < nr_channels; ++c)
+    if (!(std::fabs((freqs[c + 1] - freqs[c]) - d0) <= 1e-9 * d0)) return false;
+  return true;
+}
+
 int build_plan(const idg_params &p, const int32_t *baselines, const double *uvw, const double *freqs,
                const uint8_t *flags, HostPlan &out, std::string &err) {
   try {
     out = HostPlan{};
     out.params = p;
+    out.uniform_channels = uniform_spacing(freqs, p.nr_channels);
     Planner(p, baselines, uvw, freqs, flags, out).run();
   } catch (const std::bad_alloc &) {
     err = "idg_plan: out of host memory";

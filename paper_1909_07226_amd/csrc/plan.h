@@ -23,7 +23,13 @@ struct HostPlan {
   std::vector<uint32_t> samples;    // per planned sample: (t - t0) << 16 | (c - c0)
   std::vector<int64_t> unplanned;   // flat sample ids (bl * nt + t) * nch + c not gridded
   int64_t nr_gridded = 0, nr_dropped = 0, nr_flagged = 0;
+  bool uniform_channels = false;    // channel spacings equal to 1e-9 relative (see uniform_spacing)
 };
+
+// True when every spacing freqs[c + 1] - freqs[c] equals the first one to a
+// relative 1e-9: the phase of channel c + j is then the phase of channel c plus
+// j times one per-run step, to far below float32 resolution over short runs.
+bool uniform_spacing(const double *freqs, int nr_channels);
 
 // Builds the plan; returns IDG_OK or IDG_ENOMEM (inputs are validated by the caller).
 int build_plan(const idg_params &p, const int32_t *baselines, const double *uvw, const double *freqs,
