@@ -2,8 +2,9 @@
 
 The pins of test_oracle_pins must not pass for a wrong oracle: a flipped phase
 sign, swapped A-term order, a dropped w-term, an off-by-one subgrid centre,
-transposed l/m, a normalised or transposed subgrid DFT, or a degridder that
-applies the wrong Jones product.
+transposed l/m, a normalised or uncentred subgrid DFT, a degridder that
+applies the wrong Jones product, the pixel spacing S/(L-1), column-major Jones
+matrices, or a gridder that ignores the taper.
 """
 
 import numpy as np
@@ -19,6 +20,9 @@ PIN_TESTS = [
     pins.test_adjoint_identity,
     pins.test_classical_equivalence_single_sample,
     pins.test_integer_shift_moves_the_grid,
+    pins.test_brute_force_loops_grid,
+    pins.test_brute_force_loops_degrid,
+    lambda: pins.test_image_between_lattice_points_matches_direct_image(24),
 ]
 
 
@@ -93,8 +97,31 @@ def _degrid_wrong_jones(mp):
     mp.setattr(idg, "degrid_subgrid", degrid_subgrid)
 
 
+def _pixel_spacing_over_l_minus_1(mp):
+    # the spacing S/(L-1) that one of the algorithm listings suggests
+    def lmn(L, S):
+        idx = (np.arange(L, dtype=np.float64) - L // 2) * (S / (L - 1))
+        l, m = idx[None, :], idx[:, None]
+        return np.broadcast_to(l, (L, L)), np.broadcast_to(m, (L, L)), np.sqrt(1.0 - l * l - m * m) - 1.0
+    mp.setattr(idg, "lmn", lmn)
+
+
+def _jones_column_major(mp):
+    orig = idg._jones
+    mp.setattr(idg, "_jones", lambda aterms, slot, st, L: np.transpose(orig(aterms, slot, st, L), (0, 2, 1)))
+
+
+def _taper_ignored_in_gridding(mp):
+    orig = idg.grid_subgrid_image
+    mp.setattr(idg, "grid_subgrid_image",
+               lambda plan, p, uvw, freqs, vis, aterms, taper: orig(plan, p, uvw, freqs, vis, aterms,
+                                                                    np.ones_like(taper)))
+
+
 @pytest.mark.parametrize("mutation", [_flip_phase_sign, _drop_w, _transpose_lm, _centre_off_by_one,
-                                      _normalised_dft, _uncentred_dft, _swap_stations, _degrid_wrong_jones],
+                                      _normalised_dft, _uncentred_dft, _swap_stations, _degrid_wrong_jones,
+                                      _pixel_spacing_over_l_minus_1, _jones_column_major,
+                                      _taper_ignored_in_gridding],
                          ids=lambda f: f.__name__.strip("_"))
 def test_pins_catch_planted_mistake(mutation, monkeypatch):
     mutation(monkeypatch)

@@ -179,3 +179,154 @@ def test_integer_shift_moves_the_grid():
     g2 = idg.grid(plan2, wl2.uvw, wl2.freqs, wl2.vis, wl2.aterms, wl2.taper)
     shifted = np.roll(np.roll(g, sy, axis=1), sx, axis=2)
     assert _rel(g2, shifted) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# brute force: the algorithms written out as plain loops on a tiny case
+
+def _brute_grid(plan, wl):
+    """Algorithm 1 as nested loops: per subgrid, per pixel, per sample; then the DFT as a double sum."""
+    N, L, S = plan.grid_size, plan.subgrid_size, plan.image_size
+    g = np.zeros((4, N, N), np.complex128)
+    for p in range(plan.nr_subgrids):
+        sub = plan.subgrids[p]
+        bl, x0, y0 = sub[F["bl"]], sub[F["x0"]], sub[F["y0"]]
+        slot, s1, s2 = sub[F["slot"]], sub[F["st1"]], sub[F["st2"]]
+        u0, v0 = (x0 + L / 2 - N / 2) / S, (y0 + L / 2 - N / 2) / S
+        img = np.zeros((4, L, L), np.complex128)
+        for j in range(L):
+            for i in range(L):
+                l, m = (i - L / 2) * S / L, (j - L / 2) * S / L
+                n = np.sqrt(1.0 - l * l - m * m) - 1.0
+                acc = np.zeros((2, 2), np.complex128)
+                for t, c in plan.subgrid_samples(p):
+                    scale = wl.freqs[c] / C0
+                    u, v, w = (wl.uvw[bl, t, q] * scale for q in range(3))
+                    phase = 2.0 * np.pi * ((u - u0) * l + (v - v0) * m + w * n)
+                    acc += wl.vis[bl, t, c].astype(np.complex128).reshape(2, 2) * np.exp(1j * phase)
+                a1 = wl.aterms[slot, s1, j, i].astype(np.complex128).reshape(2, 2)
+                a2 = wl.aterms[slot, s2, j, i].astype(np.complex128).reshape(2, 2)
+                img[:, j, i] = (float(wl.taper[j, i]) * (a1.conj().T @ acc @ a2)).ravel()
+        for b in range(L):
+            for a in range(L):
+                tot = np.zeros(4, np.complex128)
+                for j in range(L):
+                    for i in range(L):
+                        tot += img[:, j, i] * np.exp(-2j * np.pi * ((a - L / 2) * (i - L / 2)
+                                                                    + (b - L / 2) * (j - L / 2)) / L)
+                g[:, y0 + b, x0 + a] += tot
+    return g
+
+
+def _brute_degrid(plan, wl, grid_in):
+    """Algorithm 2 as nested loops: split, inverse DFT as a double sum, A-terms and taper, per-sample sum."""
+    N, L, S = plan.grid_size, plan.subgrid_size, plan.image_size
+    out = np.zeros(wl.vis.shape, np.complex128)
+    for p in range(plan.nr_subgrids):
+        sub = plan.subgrids[p]
+        bl, x0, y0 = sub[F["bl"]], sub[F["x0"]], sub[F["y0"]]
+        slot, s1, s2 = sub[F["slot"]], sub[F["st1"]], sub[F["st2"]]
+        u0, v0 = (x0 + L / 2 - N / 2) / S, (y0 + L / 2 - N / 2) / S
+        bimg = np.zeros((L, L, 2, 2), np.complex128)
+        for j in range(L):
+            for i in range(L):
+                tot = np.zeros(4, np.complex128)
+                for b in range(L):
+                    for a in range(L):
+                        tot += grid_in[:, y0 + b, x0 + a] * np.exp(2j * np.pi * ((a - L / 2) * (i - L / 2)
+                                                                                 + (b - L / 2) * (j - L / 2)) / L)
+                a1 = wl.aterms[slot, s1, j, i].astype(np.complex128).reshape(2, 2)
+                a2 = wl.aterms[slot, s2, j, i].astype(np.complex128).reshape(2, 2)
+                bimg[j, i] = float(wl.taper[j, i]) * (a1 @ tot.reshape(2, 2) @ a2.conj().T)
+        for t, c in plan.subgrid_samples(p):
+            scale = wl.freqs[c] / C0
+            u, v, w = (wl.uvw[bl, t, q] * scale for q in range(3))
+            acc = np.zeros((2, 2), np.complex128)
+            for j in range(L):
+                for i in range(L):
+                    l, m = (i - L / 2) * S / L, (j - L / 2) * S / L
+                    n = np.sqrt(1.0 - l * l - m * m) - 1.0
+                    acc += bimg[j, i] * np.exp(-2j * np.pi * ((u - u0) * l + (v - v0) * m + w * n))
+            out[bl, t, c] = acc.ravel()
+    return out
+
+
+def _tiny_brute_case():
+    wl = random_track_workload(seed=17, N=32, L=8, beta=1, nbl=2, nt=6, nch=2, wscale=0.6, random_aterms=True,
+                               random_taper=True)
+    plan = plan_of(wl)
+    assert plan.nr_subgrids >= 2 and plan.nr_dropped == 0
+    return wl, plan
+
+
+def test_brute_force_loops_grid():
+    wl, plan = _tiny_brute_case()
+    g = idg.grid(plan, wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)
+    assert _rel(g, _brute_grid(plan, wl)) < 1e-12
+
+
+def test_brute_force_loops_degrid():
+    wl, plan = _tiny_brute_case()
+    rng = np.random.default_rng(23)
+    N = plan.grid_size
+    x = rng.standard_normal((4, N, N)) + 1j * rng.standard_normal((4, N, N))
+    vis = idg.degrid(plan, wl.uvw, wl.freqs, x, wl.aterms, wl.taper)
+    assert _rel(vis, _brute_degrid(plan, wl, x)) < 1e-12
+
+
+def test_linearity_in_the_visibilities():
+    wl = random_track_workload(seed=8, random_aterms=True, random_taper=True)
+    plan = plan_of(wl)
+    rng = np.random.default_rng(29)
+    y2 = (rng.standard_normal(wl.vis.shape) + 1j * rng.standard_normal(wl.vis.shape)).astype(np.complex64)
+    alpha = 0.75 - 1.25j
+    y12 = alpha * wl.vis.astype(np.complex128) + y2
+    g1 = idg.grid(plan, wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)
+    g2 = idg.grid(plan, wl.uvw, wl.freqs, y2, wl.aterms, wl.taper)
+    g12 = idg.grid(plan, wl.uvw, wl.freqs, y12, wl.aterms, wl.taper)
+    assert _rel(g12, alpha * g1 + g2) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# between the lattice points: image-domain gridding approximates the direct image
+
+@pytest.mark.parametrize("L", [24, 32])
+def test_image_between_lattice_points_matches_direct_image(L):
+    # A point source, w = 0, identity A-terms and the PSWF taper (beta = 7).  The grid's image at
+    # every master-grid image pixel, divided by L^2 times the continuous separable taper, must
+    # match the direct imaging equation (§2) to the aliasing level of the window (§4): exact
+    # only at the subgrid lattice, and growing towards the edge of the field.
+    N, beta, S = 128, 7, 1.0
+    rng = np.random.default_rng(21)
+    nbl, nt = 6, 40
+    uvw = np.zeros((nbl, nt, 3))
+    t = np.arange(nt)
+    for b in range(nbl):
+        start = rng.uniform(-N / 4, N / 4, 2)
+        vel = rng.uniform(-0.8, 0.8, 2)
+        uvw[b, :, 0] = start[0] + vel[0] * t
+        uvw[b, :, 1] = start[1] + vel[1] * t
+    l0, m0 = 0.11, -0.07
+    y = np.exp(-2j * np.pi * (uvw[..., 0] * l0 + uvw[..., 1] * m0))     # measurement equation, 1 Jy
+    vis = np.zeros((nbl, nt, 1, 4), np.complex64)
+    vis[..., 0, 0] = y
+    vis[..., 0, 3] = y
+    wl = make_mini(uvw, N=N, L=L, beta=beta, S=S, vis=vis, taper=pswf_taper_2d(L, beta))
+    plan = plan_of(wl)
+    assert plan.nr_dropped == 0 and plan.nr_subgrids > 4
+    g = idg.grid(plan, wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)[0]
+    k = np.arange(N) - N // 2
+    lx = k * S / N                                          # image pixel positions of the master grid
+    dtft = np.exp(2j * np.pi * np.outer(k, k) / N)          # exp(+2 pi i u_x l) with u_x = (x - N/2) / S
+    img = dtft @ g @ dtft.T                                 # rows m, columns l
+    alpha = beta * np.pi / 2
+    cont = np.array([pro_ang1(0, 0, alpha, 2 * li / S)[0] if abs(2 * li / S) < 1 else np.nan for li in lx])
+    cont /= pro_ang1(0, 0, alpha, 0.0)[0]
+    u, v = uvw[..., 0].ravel(), uvw[..., 1].ravel()
+    direct_img = (np.exp(2j * np.pi * np.outer(lx, v)) * y.ravel()[None, :]) @ np.exp(2j * np.pi * np.outer(u, lx))
+    peak = np.abs(direct_img).max()
+    for frac, bound in ((0.25, 3e-5), (0.35, 1e-4)):
+        keep = np.abs(lx) <= frac * S
+        est = img[np.ix_(keep, keep)] / (L * L * np.outer(cont[keep], cont[keep]))
+        err = np.abs(est - direct_img[np.ix_(keep, keep)]).max() / peak
+        assert err < bound, (L, frac, err)
