@@ -179,6 +179,8 @@ def main():
                     help="gridder/degridder schedule: autotuned (default), one workgroup per subgrid, or a "
                          "persistent work queue")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent form: workgroups per CU (0 = max)")
+    ap.add_argument("--degrid-shape", default="standard", choices=("standard", "wide"),
+                    help="degridder task shape when --form is given (autotuned otherwise)")
     ap.add_argument("--adder-chunk", type=int, default=0, help="adder: longest tile-list run per workgroup (0 = 256)")
     ap.add_argument("--serve-jobs", type=int, default=400, help="jobs in the serving trace (0 = skip serving)")
     ap.add_argument("--scratch-gb", type=float, default=0.0,
@@ -250,7 +252,7 @@ def main():
         log("[bench] autotuning the schedule (outside the timed region)")
         tune_info = autotune(plan, uvw, freqs, vis, aterms, taper, grid, vis_out, use_cache=False, log=log)
     else:
-        plan.set_tuning(form=args.form, blocks_per_cu=args.blocks_per_cu)
+        plan.set_tuning(form=args.form, blocks_per_cu=args.blocks_per_cu, degrid_shape=args.degrid_shape)
     if args.adder_chunk:
         plan.set_tuning(adder_chunk=args.adder_chunk)
     log(f"[bench] tuning {plan.get_tuning()}; warmup {args.warmup}, timing {args.steps} steps")
@@ -275,7 +277,7 @@ def main():
     tuned = plan.get_tuning()
     plain_form = None
     if args.form == "auto":
-        plan.set_tuning(form="plain", blocks_per_cu=0, adder_chunk=tuned["adder_chunk"])
+        plan.set_tuning(form="plain", blocks_per_cu=0, adder_chunk=tuned["adder_chunk"], degrid_shape="standard")
         p_ms, _ = timed(args.steps, 1)
         plain_form = {"ms_per_step": round(p_ms, 4), "value": round(nvis / (p_ms * 1e-3) / 1e6, 3)}
         log(f"[bench] plain form: {plain_form}")

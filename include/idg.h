@@ -145,19 +145,30 @@ int idg_plan_export(idg_plan_t plan, int64_t *subgrids, int32_t *samples);
  *   adder_chunk    adder: the longest run of one grid tile's subgrid list handled
  *                  by one workgroup; longer lists are summed in parallel chunks
  *                  whose partial tiles are added in order (0 = 256);
+ *   degrid_shape   IDG_DEGRID_STANDARD: degridder lanes own up to 4 visibilities
+ *                  each and sum over all pixels of their share;
+ *                  IDG_DEGRID_WIDE: subgrids with 64 or more visibilities run
+ *                  with 8 visibilities per lane over half the pixels, the two
+ *                  halves of a wave adding their sums -- fewer phasor evaluations
+ *                  per visibility, more registers; pays for large subgrids.
+ *                  Results agree to float32 summation order.  Ignored with
+ *                  IDG_PHASE_FP32;
  *   reserved       must be 0.
  * idg_plan_set_tuning validates (IDG_EINVAL) and stores the knobs; call it
  * only when no work queued with the plan is pending.  New plans start with
- * all fields 0 (plain forms, default chunk). */
+ * all fields 0 (plain forms, default chunk, standard degridder). */
 #define IDG_FORM_PLAIN 0
 #define IDG_FORM_PERSISTENT 1
+#define IDG_DEGRID_STANDARD 0
+#define IDG_DEGRID_WIDE 1
 typedef struct {
   int32_t grid_form;
   int32_t degrid_form;
   int32_t grid_blocks_per_cu;
   int32_t degrid_blocks_per_cu;
   int32_t adder_chunk;
-  int32_t reserved[3];
+  int32_t degrid_shape;
+  int32_t reserved[2];
 } idg_tuning;
 int idg_plan_set_tuning(idg_plan_t plan, const idg_tuning *tuning);
 int idg_plan_get_tuning(idg_plan_t plan, idg_tuning *tuning);

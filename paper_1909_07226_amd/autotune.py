@@ -2,12 +2,14 @@
 
 Candidates are timed on the plan's own data with the library's HIP-event stage
 timers (idg_profile): gridder and degridder in the plain form and in the
-persistent work-queue form at several workgroups per compute unit, and the
-adder at several chunk lengths.  The fastest setting of each stage wins; the
+persistent work-queue form at several workgroups per compute unit, the
+degridder in its standard and wide shapes, and the adder at several chunk
+lengths.  The fastest setting of each stage wins; the
 choice is stored on the plan and cached per (device, L, N, plan shape) in a
 JSON file (``$IDG_TUNING_CACHE`` or ``~/.cache/paper_1909_07226_amd/tuning.json``).
 Tuning changes the schedule only: results are identical for the gridder and
-degridder forms and equal up to float32 summation order for the adder chunks.
+degridder forms and equal up to float32 summation order for the degridder
+shapes and the adder chunks.
 """
 
 import json
@@ -18,6 +20,7 @@ import numpy as np
 from . import _lib
 
 GRID_CANDIDATES = (("plain", 0), ("persistent", 0), ("persistent", 1), ("persistent", 2))
+DEGRID_SHAPES = ("standard", "wide")
 CHUNK_CANDIDATES = (64, 256, 1024)
 
 
@@ -33,7 +36,7 @@ def plan_key(plan):
     mean_k = st["nr_gridded"] / n
     dev = torch.cuda.get_device_properties(torch.cuda.current_device())
     arch = getattr(dev, "gcnArchName", dev.name)
-    return (f"{arch}|L{plan.subgrid_size}|N{plan.grid_size}|P2^{int(np.log2(n))}"
+    return (f"v2|{arch}|L{plan.subgrid_size}|N{plan.grid_size}|P2^{int(np.log2(n))}"
             f"|K2^{int(np.log2(max(1.0, mean_k)))}")
 
 
@@ -103,17 +106,22 @@ def autotune(plan, uvw, freqs, vis, aterms, taper, grid, vis_out=None, reps=2, u
         do_degrid()                     # warm-up (device upload, caches)
         _lib.sync(stream)
         tg = _stage_ms(do_grid, "gridder", reps, stream)
-        td = _stage_ms(do_degrid, "degridder", reps, stream)
         timings[f"gridder/{form}/{bpc}"] = round(tg, 4)
-        timings[f"degridder/{form}/{bpc}"] = round(td, 4)
         if best_g is None or tg < best_g[0]:
             best_g = (tg, form, bpc)
-        if best_d is None or td < best_d[0]:
-            best_d = (td, form, bpc)
+        tds = []
+        for shape in DEGRID_SHAPES:
+            plan.set_tuning(degrid_shape=shape)
+            do_degrid()
+            td = _stage_ms(do_degrid, "degridder", reps, stream)
+            timings[f"degridder/{form}/{bpc}/{shape}"] = round(td, 4)
+            tds.append(f"{shape} {td:.3f} ms")
+            if best_d is None or td < best_d[0]:
+                best_d = (td, form, bpc, shape)
         if log:
-            log(f"[autotune] {form}/{bpc}: gridder {tg:.3f} ms, degridder {td:.3f} ms")
+            log(f"[autotune] {form}/{bpc}: gridder {tg:.3f} ms, degridder " + ", ".join(tds))
     plan.set_tuning(grid_form=best_g[1], grid_blocks_per_cu=best_g[2], degrid_form=best_d[1],
-                    degrid_blocks_per_cu=best_d[2])
+                    degrid_blocks_per_cu=best_d[2], degrid_shape=best_d[3])
     best_c = None
     for chunk in CHUNK_CANDIDATES:
         plan.set_tuning(adder_chunk=chunk)

@@ -389,7 +389,7 @@ int validate_params(const idg_params *p) {
 
 extern "C" {
 
-int idg_version(void) { return 10000; }
+int idg_version(void) { return 10100; }
 
 const char *idg_last_error(void) { return g_last_error.c_str(); }
 
@@ -534,10 +534,14 @@ static int alloc_grid_scratch(int64_t slots, int64_t nsub, int L, hipStream_t s,
   return IDG_OK;
 }
 
+static bool degrid_wide(const idg_plan_s *plan) {
+  return plan->tuning.degrid_shape == IDG_DEGRID_WIDE && !(plan->host.params.flags & IDG_PHASE_FP32);
+}
+
 static int persistent_blocks(const idg_plan_s *plan, const DevPlan *dp, bool degrid) {
   const int L = plan->host.params.subgrid_size;
   const int want = degrid ? plan->tuning.degrid_blocks_per_cu : plan->tuning.grid_blocks_per_cu;
-  const int per_cu = want > 0 ? want : idg::persistent_blocks_per_cu(L, degrid);
+  const int per_cu = want > 0 ? want : idg::persistent_blocks_per_cu(L, degrid, degrid && degrid_wide(plan));
   return std::max(1, per_cu * dp->nr_cus);
 }
 
@@ -636,7 +640,8 @@ int idg_degrid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, cons
     hipError_t err;
     {
       StageTimer tm(IDG_STAGE_DEGRIDDER, s);
-      err = idg::launch_degridder_persistent(L, a, dp->degrid_order, counter, persistent_blocks(plan, dp, true), s);
+      err = idg::launch_degridder_persistent(L, a, degrid_wide(plan), dp->degrid_order, counter,
+                                             persistent_blocks(plan, dp, true), s);
     }
     hipError_t ef = hipFreeAsync(counter, s);
     if (err != hipSuccess) return hip_fail(err, "idg_degrid: launch");
@@ -647,7 +652,7 @@ int idg_degrid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, cons
     a.first = f;
     a.count = int32_t(std::min<int64_t>(P - f, int64_t(1) << 30));
     StageTimer tm(IDG_STAGE_DEGRIDDER, s);
-    HIP_TRY(idg::launch_degridder(L, a, s), "idg_degrid: launch");
+    HIP_TRY(idg::launch_degridder(L, a, degrid_wide(plan), s), "idg_degrid: launch");
   }
   return IDG_OK;
 }
@@ -660,8 +665,9 @@ int idg_plan_set_tuning(idg_plan_t plan, const idg_tuning *t) {
   for (int32_t b : {t->grid_blocks_per_cu, t->degrid_blocks_per_cu})
     if (b < 0 || b > 64) return fail(IDG_EINVAL, "idg_plan_set_tuning: blocks_per_cu must be in [0, 64]");
   if (t->adder_chunk < 0) return fail(IDG_EINVAL, "idg_plan_set_tuning: adder_chunk must be >= 0");
-  if (t->reserved[0] || t->reserved[1] || t->reserved[2])
-    return fail(IDG_EINVAL, "idg_plan_set_tuning: reserved must be 0");
+  if (t->degrid_shape != IDG_DEGRID_STANDARD && t->degrid_shape != IDG_DEGRID_WIDE)
+    return fail(IDG_EINVAL, "idg_plan_set_tuning: unknown degrid_shape %d", t->degrid_shape);
+  if (t->reserved[0] || t->reserved[1]) return fail(IDG_EINVAL, "idg_plan_set_tuning: reserved must be 0");
   std::lock_guard<std::mutex> lock(plan->mu);
   const bool rebuild = t->adder_chunk != plan->tuning.adder_chunk;
   plan->tuning = *t;

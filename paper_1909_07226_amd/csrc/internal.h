@@ -72,13 +72,13 @@ struct AdderArgs {
 bool supported_subgrid_size(int L);
 
 hipError_t launch_gridder(int L, const KernelArgs &a, hipStream_t s);
-hipError_t launch_degridder(int L, const KernelArgs &a, hipStream_t s);
+hipError_t launch_degridder(int L, const KernelArgs &a, bool wide, hipStream_t s);
 // persistent forms: `order` holds a.count items, *queue_head is zeroed by the launcher
 hipError_t launch_gridder_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
                                      int nblocks, hipStream_t s);
-hipError_t launch_degridder_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
-                                       int nblocks, hipStream_t s);
-int persistent_blocks_per_cu(int L, bool degrid);
+hipError_t launch_degridder_persistent(int L, const KernelArgs &a, bool wide, const int32_t *order,
+                                       int32_t *queue_head, int nblocks, hipStream_t s);
+int persistent_blocks_per_cu(int L, bool degrid, bool wide);
 hipError_t launch_adder(int L, const AdderArgs &a, hipStream_t s);
 hipError_t launch_splitter(int L, const DevSubgrid *subgrids, int64_t first, int64_t count, const float2 *grid,
                            int grid_size, float2 *out, hipStream_t s);

@@ -506,7 +506,8 @@ __device__ __forceinline__ void degrid_pixels(float2 (&y)[V][4], const float (&d
                                               const KernelArgs &a, const float4 *s_b, const float4 *s_lmn,
                                               int lo, int hi, float u0f, float v0f) {
   constexpr bool LMN_LDS = DegridderSmem<L>::LMN_LDS;
-#pragma unroll 2
+  constexpr int UNROLL = V >= 8 ? 1 : 2;
+#pragma unroll UNROLL
   for (int pix = lo; pix < hi; ++pix) {
     const float4 q = LMN_LDS ? s_lmn[pix] : a.lmn[pix];
     const float4 b01 = s_b[2 * pix], b23 = s_b[2 * pix + 1];
@@ -542,38 +543,48 @@ __device__ __forceinline__ void degrid_pixels(float2 (&y)[V][4], const float (&d
   }
 }
 
-// A wave holds 64/Q lane groups of Q lanes; each group works on one task:
-// Q x V visibilities (lane i of the group owns the V consecutive samples
-// (chunk * Q + i) * V + v) over a 1/G share of the pixels.
-template <int L, int V, bool FP32_PHASE>
+// Output index (into vis_out, in complex units) of sample k of subgrid d.
+__device__ __forceinline__ int64_t degrid_out_index(const KernelArgs &a, const DevSubgrid &d, int k) {
+  const uint32_t pk = a.samples[d.vis_offset + k];
+  const int t = d.t0 + int(pk >> 16), c = d.c0 + int(pk & 0xffffu);
+  return ((int64_t(d.bl) * a.nr_timesteps + t) * a.nr_channels + c) * 4;
+}
+
+// A wave holds 64/(Q SPLIT) lane groups; each group works on one task: Q x V
+// visibilities (lane i of the group owns the V consecutive samples
+// (chunk * Q + i) * V + v) over a 1/G share of the pixels.  SPLIT = 2 halves
+// that share again between the two 32-lane halves of the wave (Q = 32), whose
+// sums are added by a cross-lane exchange: a lane owns twice the visibilities
+// for the same number of lanes per task.
+template <int L, int V, int SPLIT, bool FP32_PHASE>
 __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgrid &d, const float4 *s_b,
                                              const float4 *s_lmn, float4 *s_part, int G, int nchunks, int Q,
                                              double u0, double v0) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L, W = NT / 64;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int R = 64 / Q, lq = lane % Q;
+  const int TL = Q * SPLIT;  // lanes per task
+  const int R = 64 / TL, lt = lane % TL, lq = lt % Q, half = lt / Q;
   const float u0f = float(u0), v0f = float(v0);
   const int K = d.nvis;
   const bool recur = !FP32_PHASE && V > 1 && a.chan_recur != 0;
-  for (int task = wave * R + lane / Q; task < nchunks * G; task += W * R) {
+  for (int task = wave * R + lane / TL; task < nchunks * G; task += W * R) {
     const int chunk = task / G, g = task % G;
     const int kbase = (chunk * Q + lq) * V;
+    // this lane's valid samples are consecutive channels of one timestep
+    const int nv = min(V, K - kbase);
+    const uint32_t pk0 = nv > 0 ? a.samples[d.vis_offset + kbase] : 0u;
+    bool run = recur;
+    if (nv > 1) run = run && a.samples[d.vis_offset + kbase + nv - 1] == pk0 + uint32_t(nv - 1) &&
+                      int(pk0 & 0xffffu) + nv - 1 <= 0xffff;
+    const bool wave_runs = __all(run);  // uniform: the recurrence is taken by whole waves
     float du[V], dv[V], w[V];
-    int64_t out_idx[V];
-    bool valid[V];
-    uint32_t pk0 = 0;
-    bool run = recur;  // this lane's valid samples are consecutive channels of one timestep
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       const int k = kbase + v;
-      valid[v] = k < K;
       du[v] = dv[v] = w[v] = 0.0f;
-      out_idx[v] = 0;
-      if (valid[v]) {
+      if (k < K && (v == 0 || !wave_runs)) {
         const uint32_t pk = a.samples[d.vis_offset + k];
-        if (v == 0) pk0 = pk;
-        else run = run && pk == pk0 + uint32_t(v);
         const int t = d.t0 + int(pk >> 16), c = d.c0 + int(pk & 0xffffu);
         const int64_t bt = int64_t(d.bl) * a.nr_timesteps + t;
         const double *q = a.uvw + bt * 3;
@@ -588,13 +599,12 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
           dv[v] = float(q[1] * s - v0);
           w[v] = float(q[2] * s);
         }
-        if (v == 1 && run) {  // channel c - 1 is sample 0's
-          const double ds = (a.freqs[c] - a.freqs[c - 1]) / kC0;
+        if (v == 0 && wave_runs && nv > 1) {  // the step to the next channel
+          const double ds = (a.freqs[c + 1] - a.freqs[c]) / kC0;
           sx = float(q[0] * ds);
           sy = float(q[1] * ds);
           sz = float(q[2] * ds);
         }
-        out_idx[v] = (bt * a.nr_channels + c) * 4;
       }
     }
     float2 y[V][4];
@@ -602,23 +612,33 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
     for (int v = 0; v < V; ++v)
 #pragma unroll
       for (int pol = 0; pol < 4; ++pol) y[v][pol] = make_float2(0.0f, 0.0f);
-    const int lo = g * (NPIX / G), hi = lo + NPIX / G;
-    // the recurrence is taken when every active lane of the wave has a run (a uniform branch)
-    if (__all(run))
+    const int span = NPIX / G / SPLIT;
+    const int lo = g * (NPIX / G) + half * span, hi = lo + span;
+    if (wave_runs)
       degrid_pixels<L, V, FP32_PHASE, true>(y, du, dv, w, sx, sy, sz, a, s_b, s_lmn, lo, hi, u0f, v0f);
     else
       degrid_pixels<L, V, FP32_PHASE, false>(y, du, dv, w, sx, sy, sz, a, s_b, s_lmn, lo, hi, u0f, v0f);
+    if (SPLIT == 2) {
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int pol = 0; pol < 4; ++pol) {
+          y[v][pol].x += __shfl_xor(y[v][pol].x, 32);
+          y[v][pol].y += __shfl_xor(y[v][pol].y, 32);
+        }
+    }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      if (!valid[v]) continue;
+      const int k = kbase + v;
+      // with SPLIT = 2 both halves hold the sums: the lower half writes the first V/2 samples
+      if (k >= K || (SPLIT == 2 && (v < V / 2) != (half == 0))) continue;
       const float4 r0 = make_float4(y[v][0].x, y[v][0].y, y[v][1].x, y[v][1].y);
       const float4 r1 = make_float4(y[v][2].x, y[v][2].y, y[v][3].x, y[v][3].y);
       if (G == 1) {
-        float4 *o = reinterpret_cast<float4 *>(a.vis_out + out_idx[v]);
+        float4 *o = reinterpret_cast<float4 *>(a.vis_out + degrid_out_index(a, d, k));
         o[0] = r0;
         o[1] = r1;
       } else {
-        const int k = kbase + v;
         s_part[2 * (g * K + k)] = r0;
         s_part[2 * (g * K + k) + 1] = r1;
       }
@@ -626,10 +646,11 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
   }
 }
 
-
 // Degrid plan subgrid p (global index) into a.vis_out.  The caller has loaded
-// sm.tw and sm.lmn and synchronises before reusing shared memory.
-template <int L, bool FP32_PHASE>
+// sm.tw and sm.lmn and synchronises before reusing shared memory.  WIDE: tasks
+// of full-wave lane groups run in the split shape (twice the visibilities per
+// lane, two pixel halves per wave), which needs more registers.
+template <int L, bool FP32_PHASE, bool WIDE>
 __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, DegridderSmem<L> &sm) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT, W = NT / 64;
   const int tid = threadIdx.x;
@@ -695,12 +716,23 @@ __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, Degri
   const double S = a.image_size;
   const double u0 = double(d.x0 + L / 2 - N / 2) / S;
   const double v0 = double(d.y0 + L / 2 - N / 2) / S;
-  if (V == 4)
-    degrid_tasks<L, 4, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, Q, u0, v0);
-  else if (V == 2)
-    degrid_tasks<L, 2, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, Q, u0, v0);
-  else
-    degrid_tasks<L, 1, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, Q, u0, v0);
+  // WIDE: full-wave groups (Q = 64) run as two 32-lane halves over half the pixels each, with
+  // twice the visibilities per lane: the same visibilities per task, fewer phasors and pixel
+  // reads per visibility
+  if (WIDE && Q == 64) {
+    if (V == 4)
+      degrid_tasks<L, 8, 2, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, 32, u0, v0);
+    else if (V == 2)
+      degrid_tasks<L, 4, 2, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, 32, u0, v0);
+    else
+      degrid_tasks<L, 2, 2, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, 32, u0, v0);
+  } else if (V == 4) {
+    degrid_tasks<L, 4, 1, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, Q, u0, v0);
+  } else if (V == 2) {
+    degrid_tasks<L, 2, 1, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, Q, u0, v0);
+  } else {
+    degrid_tasks<L, 1, 1, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, Q, u0, v0);
+  }
   if (G > 1) {
     __syncthreads();
     for (int k = tid; k < K; k += NT) {
@@ -727,18 +759,26 @@ __device__ __forceinline__ void degrid_load_tables(const KernelArgs &a, Degridde
     for (int pix = threadIdx.x; pix < NPIX; pix += NT) sm.lmn[pix] = a.lmn[pix];
 }
 
-template <int L, bool FP32_PHASE>
-__global__ void __launch_bounds__(Cfg<L>::NT) degridder_kernel(KernelArgs a) {
+// Register budget of the WIDE degridder at L = 32: three waves per SIMD, which
+// measured faster than two waves without spills.
+template <int L, bool WIDE>
+constexpr int degrid_min_waves() {
+  return WIDE && L == 32 ? 3 : 1;
+}
+
+template <int L, bool FP32_PHASE, bool WIDE>
+__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(degrid_min_waves<L, WIDE>())))
+degridder_kernel(KernelArgs a) {
   __shared__ DegridderSmem<L> sm;
   degrid_load_tables<L>(a, sm);
-  degrid_one<L, FP32_PHASE>(a, a.first + blockIdx.x, sm);
+  degrid_one<L, FP32_PHASE, WIDE>(a, a.first + blockIdx.x, sm);
 }
 
 // Persistent form: items order[0 .. count-1] (global subgrid indices, costliest
 // first) through the counter *queue_head (zero before the launch).
-template <int L, bool FP32_PHASE>
-__global__ void __launch_bounds__(Cfg<L>::NT) degridder_persistent_kernel(KernelArgs a, const int32_t *order,
-                                                                         int32_t *queue_head) {
+template <int L, bool FP32_PHASE, bool WIDE>
+__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(degrid_min_waves<L, WIDE>())))
+degridder_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_head) {
   __shared__ DegridderSmem<L> sm;
   degrid_load_tables<L>(a, sm);
   for (;;) {
@@ -746,7 +786,7 @@ __global__ void __launch_bounds__(Cfg<L>::NT) degridder_persistent_kernel(Kernel
     __syncthreads();
     const int item = sm.next;
     if (item >= a.count) break;
-    degrid_one<L, FP32_PHASE>(a, order[item], sm);
+    degrid_one<L, FP32_PHASE, WIDE>(a, order[item], sm);
     __syncthreads();
   }
 }
@@ -930,41 +970,49 @@ hipError_t launch_gridder_persistent(int L, const KernelArgs &a, const int32_t *
   return hipGetLastError();
 }
 
-hipError_t launch_degridder(int L, const KernelArgs &a, hipStream_t s) {
+// The all-float32 phase variant has no wide form.
+hipError_t launch_degridder(int L, const KernelArgs &a, bool wide, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   IDG_DISPATCH_L(L, {
     if (a.phase_fp32)
-      hipLaunchKernelGGL((degridder_kernel<LL, true>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
+      hipLaunchKernelGGL((degridder_kernel<LL, true, false>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
+    else if (wide)
+      hipLaunchKernelGGL((degridder_kernel<LL, false, true>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
     else
-      hipLaunchKernelGGL((degridder_kernel<LL, false>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
+      hipLaunchKernelGGL((degridder_kernel<LL, false, false>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
   });
   return hipGetLastError();
 }
 
-hipError_t launch_degridder_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
-                                       int nblocks, hipStream_t s) {
+hipError_t launch_degridder_persistent(int L, const KernelArgs &a, bool wide, const int32_t *order,
+                                       int32_t *queue_head, int nblocks, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, queue_head);
   IDG_DISPATCH_L(L, {
     if (a.phase_fp32)
-      hipLaunchKernelGGL((degridder_persistent_kernel<LL, true>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a, order,
-                         queue_head);
+      hipLaunchKernelGGL((degridder_persistent_kernel<LL, true, false>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a,
+                         order, queue_head);
+    else if (wide)
+      hipLaunchKernelGGL((degridder_persistent_kernel<LL, false, true>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a,
+                         order, queue_head);
     else
-      hipLaunchKernelGGL((degridder_persistent_kernel<LL, false>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a, order,
-                         queue_head);
+      hipLaunchKernelGGL((degridder_persistent_kernel<LL, false, false>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a,
+                         order, queue_head);
   });
   return hipGetLastError();
 }
 
-int persistent_blocks_per_cu(int L, bool degrid) {
+int persistent_blocks_per_cu(int L, bool degrid, bool wide) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (L) {
 #define IDG_OCC(LL)                                                                                           \
   case LL:                                                                                                    \
-    e = degrid ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, degridder_persistent_kernel<LL, false>,     \
+    e = !degrid ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gridder_persistent_kernel<LL, false>,    \
+                                                               Cfg<LL>::NT, 0)                              \
+        : wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, degridder_persistent_kernel<LL, false, true>, \
                                                               Cfg<LL>::NT, 0)                               \
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gridder_persistent_kernel<LL, false>,     \
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, degridder_persistent_kernel<LL, false, false>, \
                                                               Cfg<LL>::NT, 0);                              \
     break;
     IDG_OCC(8)

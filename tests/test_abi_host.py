@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(idg._lib.EXPORTED)
-    assert idg.version() == 10000
+    assert idg.version() == 10100
 
 
 def _compare(wl):
@@ -142,16 +142,18 @@ def test_empty_plan():
 def test_tuning_round_trip_and_validation():
     p = idg.Plan(**_mini_params())
     assert p.get_tuning() == dict(grid_form="plain", degrid_form="plain", grid_blocks_per_cu=0,
-                                  degrid_blocks_per_cu=0, adder_chunk=0)
-    p.set_tuning(form="persistent", blocks_per_cu=3, adder_chunk=17)
+                                  degrid_blocks_per_cu=0, adder_chunk=0, degrid_shape="standard")
+    p.set_tuning(form="persistent", blocks_per_cu=3, adder_chunk=17, degrid_shape="wide")
     assert p.get_tuning() == dict(grid_form="persistent", degrid_form="persistent", grid_blocks_per_cu=3,
-                                  degrid_blocks_per_cu=3, adder_chunk=17)
+                                  degrid_blocks_per_cu=3, adder_chunk=17, degrid_shape="wide")
     p.set_tuning(degrid_form="plain", grid_blocks_per_cu=2)
     t = p.get_tuning()
     assert (t["grid_form"], t["degrid_form"], t["grid_blocks_per_cu"], t["degrid_blocks_per_cu"]) == (
         "persistent", "plain", 2, 3)
-    for bad in (dict(form=7), dict(blocks_per_cu=-1), dict(degrid_blocks_per_cu=65), dict(adder_chunk=-2)):
+    for bad in (dict(form=7), dict(blocks_per_cu=-1), dict(degrid_blocks_per_cu=65), dict(adder_chunk=-2),
+                dict(degrid_shape=2)):
         with pytest.raises(idg.IDGError) as e:
             p.set_tuning(**bad)
         assert e.value.code == -1
     assert p.get_tuning()["adder_chunk"] == 17          # unchanged by the rejected calls
+    assert p.get_tuning()["degrid_shape"] == "wide"

@@ -83,15 +83,17 @@ def test_many_channel_subgrids(gpu, name):
     rng = np.random.default_rng(4)
     N = wl.grid_size
     grid_in = (rng.standard_normal((4, N, N)) + 1j * rng.standard_normal((4, N, N))).astype(np.complex64)
-    v = torch.full(tuple(wl.vis.shape), 3.0 - 1.0j, dtype=torch.complex64, device="cuda")
-    idg.degrid(plan, d["uvw"], d["freqs"], torch.from_numpy(grid_in).cuda(), d["aterms"], d["taper"], v)
-    idg.sync()
     vref = oidg.degrid(oplan, wl.uvw, wl.freqs, grid_in, wl.aterms, wl.taper)
-    got = v.cpu().numpy()
     planned = np.zeros(wl.vis.shape[:3], bool)
     for p in range(oplan.nr_subgrids):
         tc = oplan.subgrid_samples(p)
         planned[oplan.subgrids[p, F["bl"]], tc[:, 0], tc[:, 1]] = True
-    say(f"    vis rms rel {rms_rel(got[planned], vref[planned]):.2e}")
-    assert rms_rel(got[planned], vref[planned]) < VIS_RMS_TOL
-    assert np.all(got[~planned] == 0)
+    for shape in ("standard", "wide"):
+        plan.set_tuning(degrid_shape=shape)
+        v = torch.full(tuple(wl.vis.shape), 3.0 - 1.0j, dtype=torch.complex64, device="cuda")
+        idg.degrid(plan, d["uvw"], d["freqs"], torch.from_numpy(grid_in).cuda(), d["aterms"], d["taper"], v)
+        idg.sync()
+        got = v.cpu().numpy()
+        say(f"    {shape} degridder: vis rms rel {rms_rel(got[planned], vref[planned]):.2e}")
+        assert rms_rel(got[planned], vref[planned]) < VIS_RMS_TOL, shape
+        assert np.all(got[~planned] == 0)

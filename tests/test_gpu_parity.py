@@ -231,13 +231,15 @@ def test_every_subgrid_size(gpu, L):
     g = _grid_gpu(torch, idg, wl, plan, d).cpu().numpy()
     ref = oidg.grid(oplan, wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)
     assert rms_rel(g, ref) < GRID_RMS_TOL
-    vis = torch.empty(tuple(wl.vis.shape), dtype=torch.complex64, device="cuda")
-    idg.degrid(plan, d["uvw"], d["freqs"], torch.from_numpy(ref.astype(np.complex64)).cuda(), d["aterms"],
-               d["taper"], vis)
-    idg.sync()
     vref = oidg.degrid(oplan, wl.uvw, wl.freqs, ref.astype(np.complex64), wl.aterms, wl.taper)
     planned = np.abs(vref).sum(-1) > 0
-    assert rms_rel(vis.cpu().numpy()[planned], vref[planned]) < VIS_RMS_TOL
+    for shape in ("standard", "wide"):
+        plan.set_tuning(degrid_shape=shape)
+        vis = torch.empty(tuple(wl.vis.shape), dtype=torch.complex64, device="cuda")
+        idg.degrid(plan, d["uvw"], d["freqs"], torch.from_numpy(ref.astype(np.complex64)).cuda(), d["aterms"],
+                   d["taper"], vis)
+        idg.sync()
+        assert rms_rel(vis.cpu().numpy()[planned], vref[planned]) < VIS_RMS_TOL, shape
 
 
 def test_edge_subgrids_and_single_sample_blocks(gpu):
@@ -298,6 +300,44 @@ def test_persistent_form_equals_plain(gpu, name):
         out[form] = (g, v)
     assert torch.equal(out["plain"][0], out["persistent"][0])
     assert torch.equal(out["plain"][1], out["persistent"][1])
+
+
+@pytest.mark.parametrize("name", ["lofar-subset", "skalow-subset-flags", "tracks-L16-aterms-w"])
+def test_wide_degridder_shape(gpu, name):
+    # the wide shape (8 visibilities per lane, pixel halves added across the wave) against the
+    # oracle; its persistent form is bitwise equal to its plain form
+    torch, idg = gpu
+    wl, oplan = _case(name)
+    say(f"[wide degridder] case={name}")
+    assert oplan.subgrids[:, F["nvis"]].max() >= 64        # the wide tasks do occur
+    d = to_dev(wl)
+    rng = np.random.default_rng(5)
+    N = wl.grid_size
+    grid_in = np.zeros((4, N, N), np.complex64)
+    for p in range(oplan.nr_subgrids):
+        x0, y0, L = oplan.subgrids[p, F["x0"]], oplan.subgrids[p, F["y0"]], wl.subgrid_size
+        grid_in[:, y0:y0 + L, x0:x0 + L] = 1.0
+    mask = grid_in != 0
+    grid_in[mask] = (rng.standard_normal(mask.sum()) + 1j * rng.standard_normal(mask.sum())).astype(np.complex64)
+    gdev = torch.from_numpy(grid_in).cuda()
+    ref = oidg.degrid(oplan, wl.uvw, wl.freqs, grid_in, wl.aterms, wl.taper)
+    planned = np.zeros(wl.vis.shape[:3], bool)
+    for p in range(oplan.nr_subgrids):
+        tc = oplan.subgrid_samples(p)
+        planned[oplan.subgrids[p, F["bl"]], tc[:, 0], tc[:, 1]] = True
+    out = {}
+    for form in ("plain", "persistent"):
+        plan = idg.Plan.from_workload(wl)
+        plan.set_tuning(form=form, degrid_shape="wide")
+        v = torch.full(tuple(wl.vis.shape), 5.0 + 5.0j, dtype=torch.complex64, device="cuda")
+        idg.degrid(plan, d["uvw"], d["freqs"], gdev, d["aterms"], d["taper"], v)
+        idg.sync()
+        out[form] = v
+    got = out["plain"].cpu().numpy()
+    say(f"    vis rms rel {rms_rel(got[planned], ref[planned]):.2e}")
+    assert rms_rel(got[planned], ref[planned]) < VIS_RMS_TOL
+    assert np.all(got[~planned] == 0)
+    assert torch.equal(out["plain"], out["persistent"])
 
 
 def test_adder_chunks_split_long_tile_lists(gpu):
