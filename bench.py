@@ -126,6 +126,70 @@ def cpu_baseline(wl, budget_s):
             "grid_s": round(t1 - t0, 3), "degrid_s": round(t2 - t1, 3)}
 
 
+HBM_PEAK_GBS = 8000.0               # MI355X HBM3E
+
+
+def touched_tile_count(plan, tile=32):
+    """Number of distinct tile x tile grid tiles that the plan's subgrids overlap."""
+    sub, _ = plan.export()
+    from paper_1909_07226_amd._lib import SUBGRID_FIELDS
+    F = {n: i for i, n in enumerate(SUBGRID_FIELDS)}
+    L = plan.subgrid_size
+    x0, y0 = sub[:, F["x0"]], sub[:, F["y0"]]
+    ntx = -(-plan.grid_size // tile)
+    span = L // tile + 2
+    ids = []
+    for dy in range(span):
+        for dx in range(span):
+            tx, ty = x0 // tile + dx, y0 // tile + dy
+            ok = (tx <= (x0 + L - 1) // tile) & (ty <= (y0 + L - 1) // tile)
+            ids.append((ty * ntx + tx)[ok])
+    return int(np.unique(np.concatenate(ids)).size)
+
+
+def hbm_stages(idg, torch, plan, grid, stream, adder_ms_per_step, log, max_subgrids=65536, reps=5):
+    """HBM rates of the memory-bound stages against the 8 TB/s peak.
+
+    splitter (idg_split_subgrids) and the batched subgrid transform
+    (idg_subgrid_fft, in place) run standalone here; inside idg_degrid and
+    idg_grid they are fused and move no HBM bytes of their own.  Algorithmic
+    bytes: the splitter reads and writes 4 L^2 x 8 bytes per subgrid, the
+    transform the same; the adder (timed inside idg_grid) reads every subgrid
+    once and reads and writes every touched grid tile once.
+    """
+    L = plan.subgrid_size
+    P = plan.stats()["nr_subgrids"]
+    n = min(P, max_subgrids)
+    sub_bytes = 4 * L * L * 8
+    buf = torch.empty((n, 4, L, L), dtype=torch.complex64, device="cuda")
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    t = timed(lambda: idg.split_subgrids(plan, grid, 0, buf, stream))
+    out["splitter"] = dict(ms=round(t, 4), bytes=2 * n * sub_bytes, subgrids=n)
+    t = timed(lambda: idg.subgrid_fft(buf, -1, stream))
+    out["subgrid_fft"] = dict(ms=round(t, 4), bytes=2 * n * sub_bytes, subgrids=n)
+    tiles = touched_tile_count(plan)
+    out["adder"] = dict(ms=round(adder_ms_per_step, 4), bytes=P * sub_bytes + 2 * tiles * 4 * 32 * 32 * 8,
+                        subgrids=P, touched_tiles=tiles)
+    for k, v in out.items():
+        gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+        v["gb_s"] = round(gbs, 1)
+        v["frac"] = round(gbs / HBM_PEAK_GBS, 4)
+        log(f"[bench] {k}: {v['bytes'] / 1e9:.3f} GB in {v['ms']:.3f} ms = {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.1%})")
+    del buf
+    return out
+
+
 def serving_leg(lofar_wl, lofar_dev, n_jobs, log):
     """Replay one request trace twice: continuous batching (4 slots, persistent form) and a FIFO
     (1 slot, plain form).  p50/p99 of completion - arrival."""
@@ -318,6 +382,7 @@ def main():
         "autotune_ms": tune_info["timings_ms"] if tune_info else None,
         "cpu_baseline": None,
     }
+    result["hbm_stages"] = hbm_stages(idg, torch, plan, grid, stream, a_ms / k, log)
     if args.serve_jobs > 0 and args.workload == "lofar":
         result["serving"] = serving_leg(wl, dict(uvw=uvw, freqs=freqs, vis=vis, aterms=aterms, taper=taper),
                                         args.serve_jobs, log)

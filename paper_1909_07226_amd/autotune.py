@@ -21,7 +21,7 @@ from . import _lib
 
 GRID_CANDIDATES = (("plain", 0), ("persistent", 0), ("persistent", 1), ("persistent", 2))
 DEGRID_SHAPES = ("standard", "wide")
-CHUNK_CANDIDATES = (64, 256, 1024)
+CHUNK_CANDIDATES = (32, 64, 256, 1024)
 
 
 def _cache_path():

@@ -459,10 +459,18 @@ __global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
 
 // Persistent form: items order[0 .. count-1] (local subgrid indices, costliest
 // first) are taken one at a time through the counter *queue_head (zero before
-// the launch).  Every workgroup leaves once the counter passes the end.
+// the launch).  Every workgroup leaves once the counter passes the end.  At
+// L = 32 it is held to 4 waves per SIMD like the one-subgrid form (which needs
+// 120 VGPRs); the persistent loop otherwise takes 150 (3 waves), and 4 waves
+// with 18 spilled VGPRs measured faster.
+template <int L>
+constexpr int grid_persistent_min_waves() {
+  return L == 32 ? 4 : 1;
+}
+
 template <int L, bool FP32_PHASE>
-__global__ void __launch_bounds__(Cfg<L>::NT) gridder_persistent_kernel(KernelArgs a, const int32_t *order,
-                                                                       int32_t *queue_head) {
+__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(grid_persistent_min_waves<L>())))
+gridder_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_head) {
   __shared__ GridderSmem<L> sm;
   if (threadIdx.x < L) sm.tw[threadIdx.x] = a.twiddle[threadIdx.x];
   PixelCoords<L> pc;
@@ -759,11 +767,13 @@ __device__ __forceinline__ void degrid_load_tables(const KernelArgs &a, Degridde
     for (int pix = threadIdx.x; pix < NPIX; pix += NT) sm.lmn[pix] = a.lmn[pix];
 }
 
-// Register budget of the WIDE degridder at L = 32: three waves per SIMD, which
-// measured faster than two waves without spills.
+// Register budgets at L = 32 (waves per SIMD): the standard degridder 4 (its
+// persistent form spills 8 VGPRs, and ran 16 % faster on small subgrids than
+// at 3 waves without spills); the wide degridder 3 (spills 22 VGPRs; faster
+// than 2 waves without spills).  Other sizes: as the compiler chooses.
 template <int L, bool WIDE>
 constexpr int degrid_min_waves() {
-  return WIDE && L == 32 ? 3 : 1;
+  return L == 32 ? (WIDE ? 3 : 4) : 1;
 }
 
 template <int L, bool FP32_PHASE, bool WIDE>
