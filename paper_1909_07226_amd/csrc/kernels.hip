@@ -109,7 +109,7 @@ __device__ __forceinline__ void apply_aterms_degrid(const float2 *j1, const floa
 
 template <int L>
 struct SgLayout {
-  static constexpr bool FFT = (L == 8 || L == 16 || L == 32);
+  static constexpr bool FFT = (L == 8 || L == 16 || L == 32 || L == 64);
   static constexpr int RS = FFT ? L + 1 : L;  // row stride
   static constexpr int POL = L * RS;          // polarisation stride
   static constexpr int SIZE = 4 * POL;        // complex elements
@@ -204,22 +204,68 @@ __device__ __forceinline__ void lds_centred_dft(float2 *sg, const float2 *tw) {
   constexpr int NPIX = L * L, PPT = NPIX / NT, H = L / 2;
   const int tid = threadIdx.x;
   if constexpr (Lay::FFT) {
+    // Each line (a row in pass 0, a column in pass 1, of one polarisation) is
+    // transformed by two threads: thread h takes the samples n = 2j + h and does
+    // an L/2-point FFT in registers; after a barrier, each thread forms half of
+    // the radix-2 butterflies X0[k] +- W^k X1[k].  Work item w: the two halves of
+    // a wave take the same 32 lines (h = 0, then h = 1), so that the 32 lanes of
+    // a half-wave walk 32 different lines, as in a one-thread-per-line layout.
+    constexpr int HL = L / 2, QL = L / 4, ROUNDS = (8 * L + NT - 1) / NT;
+    static_assert((8 * L) % 64 == 0, "work items fill whole waves");
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
-      for (int line = tid; line < 4 * L; line += NT) {
+      const int step = pass == 0 ? 1 : Lay::RS;
+      for (int w = tid; w < 8 * L; w += NT) {
+        const int line = (w >> 6) * 32 + (w & 31), h = (w >> 5) & 1;
         const int pol = line / L, q = line % L;  // q: row (pass 0) or column (pass 1)
         float2 *base = sg + pol * Lay::POL + (pass == 0 ? q * Lay::RS : q);
-        const int step = pass == 0 ? 1 : Lay::RS;
-        float2 x[L];
+        float2 x[HL];
 #pragma unroll
-        for (int n = 0; n < L; ++n) {
+        for (int j = 0; j < HL; ++j) {
+          const int n = 2 * j + h;
           const float2 v = base[n * step];
           const bool flip = pass == 0 && ((n + q) & 1);
-          x[n] = flip ? make_float2(-v.x, -v.y) : v;
+          x[j] = flip ? make_float2(-v.x, -v.y) : v;
         }
-        reg_fft<L, INV>(x);
+        reg_fft<HL, INV>(x);
 #pragma unroll
-        for (int k = 0; k < L; ++k) base[k * step] = (k & 1) ? make_float2(-x[k].x, -x[k].y) : x[k];
+        for (int k = 0; k < HL; ++k) base[(2 * k + h) * step] = x[k];  // X_h[k] where sample 2k + h was
+      }
+      __syncthreads();
+      float2 y[ROUNDS][2][QL];
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        const int w = tid + r * NT;
+        if (w >= 8 * L) break;
+        const int line = (w >> 6) * 32 + (w & 31), h = (w >> 5) & 1;
+        const int pol = line / L, q = line % L;
+        const float2 *base = sg + pol * Lay::POL + (pass == 0 ? q * Lay::RS : q);
+#pragma unroll
+        for (int i = 0; i < QL; ++i) {
+          const int k = h * QL + i;
+          const float2 a0 = base[(2 * k) * step], b0 = base[(2 * k + 1) * step];
+          float2 t = tw[k];  // exp(-2 pi i k / L)
+          if (INV) t.y = -t.y;
+          const float2 bw = make_float2(b0.x * t.x - b0.y * t.y, b0.x * t.y + b0.y * t.x);
+          y[r][0][i] = make_float2(a0.x + bw.x, a0.y + bw.y);
+          y[r][1][i] = make_float2(a0.x - bw.x, a0.y - bw.y);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        const int w = tid + r * NT;
+        if (w >= 8 * L) break;
+        const int line = (w >> 6) * 32 + (w & 31), h = (w >> 5) & 1;
+        const int pol = line / L, q = line % L;
+        float2 *base = sg + pol * Lay::POL + (pass == 0 ? q * Lay::RS : q);
+#pragma unroll
+        for (int i = 0; i < QL; ++i) {
+          const int k = h * QL + i;  // outputs k and k + L/2; both have the parity of k
+          const float2 v0 = y[r][0][i], v1 = y[r][1][i];
+          base[k * step] = (k & 1) ? make_float2(-v0.x, -v0.y) : v0;
+          base[(k + HL) * step] = ((k + HL) & 1) ? make_float2(-v1.x, -v1.y) : v1;
+        }
       }
       __syncthreads();
     }
