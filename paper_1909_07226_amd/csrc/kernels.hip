@@ -780,6 +780,15 @@ __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, Degri
       degrid_tasks<L, 4, 2, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, 32, u0, v0);
     else
       degrid_tasks<L, 2, 2, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, 32, u0, v0);
+  } else if (Q == 32 && nchunks * G <= W) {
+    // small subgrids whose tasks fit one per wave: both halves of the wave work on a task
+    // (each over half of its pixels), so that twice the lanes are busy
+    if (V == 4)
+      degrid_tasks<L, 4, 2, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, 32, u0, v0);
+    else if (V == 2)
+      degrid_tasks<L, 2, 2, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, 32, u0, v0);
+    else
+      degrid_tasks<L, 1, 2, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, 32, u0, v0);
   } else if (V == 4) {
     degrid_tasks<L, 4, 1, FP32_PHASE>(a, d, s_b, sm.lmn, sm.part, G, nchunks, Q, u0, v0);
   } else if (V == 2) {
