@@ -185,8 +185,13 @@ void idg_plan_destroy(idg_plan_t plan);
  * DFT; and the sum into grid_d at corner (x0, y0).  grid_d is ACCUMULATED
  * into (the caller zeroes it).  Results are deterministic: for each grid tile
  * the subgrids are added in plan order.  uvw_d and freqs_d must hold the
- * values given to idg_plan.  Device scratch of at most params.scratch_bytes is
- * allocated stream-ordered for the call.
+ * values given to idg_plan.  When idg_plan found the channel frequencies
+ * evenly spaced (every spacing equal to the first to 1e-9 relative), the
+ * phasors of consecutive channels of one timestep are advanced by one complex
+ * multiplication with a per-run step phasor (runs of at most 16 channels)
+ * instead of a sin/cos per sample; the result agrees with the per-sample
+ * evaluation to float32 rounding.  Device scratch of at most
+ * params.scratch_bytes is allocated stream-ordered for the call.
  *
  *   uvw_d    float64 [nr_baselines][nr_timesteps][3]     freqs_d  float64 [nr_channels]
  *   vis_d    complex64 [nr_baselines][nr_timesteps][nr_channels][4]
