@@ -1,0 +1,49 @@
+"""Master grid <-> image (the steps around the hot path), in float64 (oracle).
+
+Test infrastructure only: nothing in the library calls this module.
+
+Algorithm 1 ends with the transform of the master grid to the image domain
+and the division by the taper; Algorithm 2 starts from the model image
+divided by the taper and transformed to the uv grid (§3.3: the subgrid
+images approximate the image multiplied by the taper, so the image is the
+transform of the grid divided by it).  Conventions (the readings are kept with
+the design notes of the repository):
+
+* grid G[pol][v][u] with u_u = (u - N/2) / S; image I[pol][y][x] at
+  l_x = (x - N/2) S / N, m_y = (y - N/2) S / N (§2 pixel positions with N
+  pixels across S), so u_u l_x = (u - N/2)(x - N/2) / N exactly;
+* grid_to_image: I[y][x] = sum_{v,u} G[v][u] exp(+2 pi i ((u - N/2)(x - N/2) +
+  (v - N/2)(y - N/2)) / N) / (corr_m[y] corr_l[x]), the grid's DTFT at the image
+  pixels divided by a separable correction (for the taper c of the subgrids,
+  corr_l[x] = L c(l_x), which makes the division by L^2 c(l) c(m));
+* image_to_grid: its adjoint, G[v][u] = sum_{y,x} I[y][x] / (corr_m[y] corr_l[x])
+  exp(-2 pi i (...) / N).
+"""
+
+import numpy as np
+
+
+def centred_dft(N, sign):
+    """D[a, b] = exp(sign 2 pi i (a - N/2)(b - N/2) / N), exact integer phase mod N."""
+    k = np.arange(N, dtype=np.int64) - N // 2
+    r = np.mod(np.outer(k, k), N).astype(np.float64)
+    return np.exp(sign * 2j * np.pi * r / N)
+
+
+def grid_to_image(grid, corr_l, corr_m):
+    """Image [4, N, N] complex128 from grid [4, N, N]: the grid's DTFT at the image pixels / correction."""
+    g = np.asarray(grid, np.complex128)
+    N = g.shape[-1]
+    d = centred_dft(N, +1)                  # d[x, u]
+    corr = np.outer(np.asarray(corr_m, np.float64), np.asarray(corr_l, np.float64))
+    return np.stack([d @ g[p] @ d.T for p in range(g.shape[0])]) / corr
+
+
+def image_to_grid(image, corr_l, corr_m):
+    """Grid [4, N, N] complex128 from image [4, N, N]: the adjoint of grid_to_image."""
+    im = np.asarray(image, np.complex128)
+    N = im.shape[-1]
+    d = centred_dft(N, -1)                  # d[u, x]
+    corr = np.outer(np.asarray(corr_m, np.float64), np.asarray(corr_l, np.float64))
+    x = im / corr
+    return np.stack([d @ x[p] @ d.T for p in range(im.shape[0])])
