@@ -155,7 +155,9 @@ def hbm_stages(idg, torch, plan, grid, stream, adder_ms_per_step, log, max_subgr
     idg_grid they are fused and move no HBM bytes of their own.  Algorithmic
     bytes: the splitter reads and writes 4 L^2 x 8 bytes per subgrid, the
     transform the same; the adder (timed inside idg_grid) reads every subgrid
-    once and reads and writes every touched grid tile once.
+    once and reads and writes every touched grid tile once.  The master grid
+    <-> image steps (idg_grid_to_image, idg_image_to_grid) overwrite `grid`
+    with the round trip of its contents.
     """
     L = plan.subgrid_size
     P = plan.stats()["nr_subgrids"]
@@ -178,6 +180,19 @@ def hbm_stages(idg, torch, plan, grid, stream, adder_ms_per_step, log, max_subgr
     out["splitter"] = dict(ms=round(t, 4), bytes=2 * n * sub_bytes, subgrids=n)
     t = timed(lambda: idg.subgrid_fft(buf, -1, stream))
     out["subgrid_fft"] = dict(ms=round(t, 4), bytes=2 * n * sub_bytes, subgrids=n)
+    # master grid <-> image (four passes over the [4, N, N] array: rows, transpose, rows, transpose);
+    # algorithmic bytes are one read of the input and one write of the output
+    N = grid.shape[-1]
+    corr = torch.ones(N, dtype=torch.float32, device="cuda")
+    img = torch.empty_like(grid)
+    arr = 4 * N * N * 8
+    t = timed(lambda: idg.grid_to_image(grid, corr, corr, img, stream))
+    out["grid_to_image"] = dict(ms=round(t, 4), bytes=2 * arr, grid_size=N, passes=4,
+                                pass_gb_s=round(8 * arr / (t * 1e-3) / 1e9, 1))
+    t = timed(lambda: idg.image_to_grid(img, corr, corr, grid, stream))
+    out["image_to_grid"] = dict(ms=round(t, 4), bytes=2 * arr, grid_size=N, passes=4,
+                                pass_gb_s=round(8 * arr / (t * 1e-3) / 1e9, 1))
+    del img
     tiles = touched_tile_count(plan)
     out["adder"] = dict(ms=round(adder_ms_per_step, 4), bytes=P * sub_bytes + 2 * tiles * 4 * 32 * 32 * 8,
                         subgrids=P, touched_tiles=tiles)

@@ -252,6 +252,35 @@ int idg_add_subgrids(idg_plan_t plan, const idg_cf32 *subgrids_d, int64_t first,
 int idg_split_subgrids(idg_plan_t plan, const idg_cf32 *grid_d, int64_t first, int64_t count, idg_cf32 *subgrids_d,
                        void *stream);
 
+/*
+ * Master grid -> image (the last line of Algorithm 1; §3.3: the image is the
+ * transform of the grid divided by the taper):
+ *   image_d[pol][y][x] = sum_{v,u} grid_d[pol][v][u]
+ *                        exp(+2 pi i ((u - N/2)(x - N/2) + (v - N/2)(y - N/2)) / N)
+ *                        / (corr_m_d[y] corr_l_d[x]),
+ * i.e. the grid's DTFT at the image pixels l_x = (x - N/2) S / N, m_y = (y -
+ * N/2) S / N, divided by a separable correction (for subgrids with taper c,
+ * corr[x] = L c(l_x) gives the division by L^2 c(l) c(m)).  Unnormalised.
+ *   grid_d    device complex64 [4][N][N], read
+ *   corr_l_d, corr_m_d  device float32 [N] (both NULL: no division)
+ *   image_d   device complex64 [4][N][N], OVERWRITTEN; must not overlap grid_d
+ * N = grid_size must be a power of two in [64, 16384].  Device scratch of
+ * 4 N^2 x 8 bytes is allocated stream-ordered for the call.
+ * Errors: IDG_EINVAL (size, NULL or overlapping buffers), IDG_ENOMEM, IDG_EHIP.
+ */
+int idg_grid_to_image(const idg_cf32 *grid_d, int32_t grid_size, const float *corr_l_d, const float *corr_m_d,
+                      idg_cf32 *image_d, void *stream);
+
+/*
+ * Image -> master grid (the first lines of Algorithm 2, model image divided by
+ * the taper and transformed), the adjoint of idg_grid_to_image:
+ *   grid_d[pol][v][u] = sum_{y,x} image_d[pol][y][x] / (corr_m_d[y] corr_l_d[x])
+ *                       exp(-2 pi i ((u - N/2)(x - N/2) + (v - N/2)(y - N/2)) / N).
+ * grid_d is OVERWRITTEN.  Arguments and errors as idg_grid_to_image.
+ */
+int idg_image_to_grid(const idg_cf32 *image_d, int32_t grid_size, const float *corr_l_d, const float *corr_m_d,
+                      idg_cf32 *grid_d, void *stream);
+
 /* Stage timing (the library's own tracing).  While enabled, idg_grid and
  * idg_degrid record a pair of HIP events on their stream around every kernel
  * they queue.  idg_profile_read waits for the recorded events and returns the

@@ -47,3 +47,38 @@ def image_to_grid(image, corr_l, corr_m):
     corr = np.outer(np.asarray(corr_m, np.float64), np.asarray(corr_l, np.float64))
     x = im / corr
     return np.stack([d @ x[p] @ d.T for p in range(im.shape[0])])
+
+
+def _centred_row(N, k, sign):
+    """exp(sign 2 pi i (j - N/2)(k - N/2) / N) over j = 0 .. N-1, exact integer phase mod N."""
+    j = np.arange(N, dtype=np.int64) - N // 2
+    r = np.mod(j * (int(k) - N // 2), N).astype(np.float64)
+    return np.exp(sign * 2j * np.pi * r / N)
+
+
+def grid_to_image_at(grid, xs, ys, corr_l, corr_m):
+    """image[:, ys[i], xs[i]] of grid_to_image, one pixel at a time (for grids too large for the whole transform)."""
+    g = np.asarray(grid)
+    N = g.shape[-1]
+    out = np.zeros((g.shape[0], len(xs)), np.complex128)
+    for p in range(g.shape[0]):
+        gp = g[p].astype(np.complex128)
+        for i, (x, y) in enumerate(zip(xs, ys)):
+            dx, dy = _centred_row(N, x, +1), _centred_row(N, y, +1)
+            out[p, i] = dy @ (gp @ dx) / (float(corr_m[y]) * float(corr_l[x]))
+    return out
+
+
+def image_to_grid_at(image, us, vs, corr_l, corr_m):
+    """grid[:, vs[i], us[i]] of image_to_grid, one cell at a time."""
+    im = np.asarray(image)
+    N = im.shape[-1]
+    cl = 1.0 / np.asarray(corr_l, np.float64)
+    cm = 1.0 / np.asarray(corr_m, np.float64)
+    out = np.zeros((im.shape[0], len(us)), np.complex128)
+    for p in range(im.shape[0]):
+        ip = im[p].astype(np.complex128)
+        for i, (u, v) in enumerate(zip(us, vs)):
+            du, dv = _centred_row(N, u, -1) * cl, _centred_row(N, v, -1) * cm
+            out[p, i] = dv @ (ip @ du)
+    return out

@@ -17,6 +17,8 @@ from ._lib import (  # noqa: F401
     degrid,
     grid,
     grid_subgrids,
+    grid_to_image,
+    image_to_grid,
     lib,
     profile,
     profile_read,

@@ -22,7 +22,7 @@ SUBGRID_FIELDS = ("bl", "t0", "nt", "c0", "nc", "x0", "y0", "slot", "s1", "s2", 
 EXPORTED = ("idg_plan", "idg_plan_stats", "idg_plan_export", "idg_plan_destroy", "idg_grid", "idg_degrid",
             "idg_grid_subgrids", "idg_subgrid_fft", "idg_add_subgrids", "idg_split_subgrids", "idg_sync",
             "idg_last_error", "idg_version", "idg_profile", "idg_profile_read", "idg_plan_set_tuning",
-            "idg_plan_get_tuning")
+            "idg_plan_get_tuning", "idg_grid_to_image", "idg_image_to_grid")
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 DEGRID_STANDARD, DEGRID_WIDE = 0, 1
 STAGES = ("gridder", "adder", "degridder", "zero")
@@ -84,6 +84,8 @@ def lib():
         L.idg_profile_read.argtypes = [vp, vp, ctypes.c_int]
         L.idg_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.idg_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.idg_grid_to_image.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.idg_image_to_grid.argtypes = [vp, i32, vp, vp, vp, vp]
         for name in EXPORTED:
             if name not in ("idg_plan_destroy", "idg_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -291,6 +293,32 @@ def split_subgrids(plan, grid_d, first, out_d, stream=None):
     check(lib().idg_split_subgrids(plan.handle, _dev_ptr(grid_d, torch.complex64, plan.shapes()["grid"], "grid"),
                                    int(first), count, _dev_ptr(out_d, torch.complex64, (count, 4, L, L), "out"),
                                    _stream_ptr(stream)))
+
+
+def _image_args(src_d, dst_d, corr_l_d, corr_m_d):
+    import torch
+    if src_d.dim() != 3 or src_d.shape[0] != 4 or src_d.shape[1] != src_d.shape[2]:
+        raise ValueError("expected a [4, N, N] complex64 array")
+    N = int(src_d.shape[-1])
+    src = _dev_ptr(src_d, torch.complex64, (4, N, N), "input")
+    dst = _dev_ptr(dst_d, torch.complex64, (4, N, N), "output")
+    if (corr_l_d is None) != (corr_m_d is None):
+        raise ValueError("give both corrections or neither")
+    cl = None if corr_l_d is None else _dev_ptr(corr_l_d, torch.float32, (N,), "corr_l")
+    cm = None if corr_m_d is None else _dev_ptr(corr_m_d, torch.float32, (N,), "corr_m")
+    return src, N, cl, cm, dst
+
+
+def grid_to_image(grid_d, corr_l_d, corr_m_d, image_d, stream=None):
+    """idg_grid_to_image: image_d [4, N, N] = the grid's DTFT at the image pixels / (corr_m[y] corr_l[x])."""
+    src, N, cl, cm, dst = _image_args(grid_d, image_d, corr_l_d, corr_m_d)
+    check(lib().idg_grid_to_image(src, N, cl, cm, dst, _stream_ptr(stream)))
+
+
+def image_to_grid(image_d, corr_l_d, corr_m_d, grid_d, stream=None):
+    """idg_image_to_grid: grid_d [4, N, N] = the adjoint transform of image_d / (corr_m[y] corr_l[x])."""
+    src, N, cl, cm, dst = _image_args(image_d, grid_d, corr_l_d, corr_m_d)
+    check(lib().idg_image_to_grid(src, N, cl, cm, dst, _stream_ptr(stream)))
 
 
 def sync(stream=None):

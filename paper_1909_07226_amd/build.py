@@ -46,7 +46,7 @@ def build(verbose=False):
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src, lang in (("kernels.hip", "hip"), ("api.cpp", "hip")):
+    for src, lang in (("kernels.hip", "hip"), ("image.hip", "hip"), ("api.cpp", "hip")):
         obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
         _run([hipcc, "-x", lang, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)

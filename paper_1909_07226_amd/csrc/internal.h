@@ -86,4 +86,14 @@ hipError_t launch_subgrid_fft(int L, float2 *data, int64_t count, int direction,
                               hipStream_t s);
 hipError_t launch_zero_samples(const int64_t *ids, int64_t n, float2 *vis, hipStream_t s);
 
+// master grid <-> image (image.hip)
+bool image_size_supported(int N);
+hipError_t launch_image_twiddles(float2 *tw, int N, hipStream_t s);
+// centred length-N transform of each of nrows contiguous rows (out may equal in); sign +1: exp(+...)
+hipError_t launch_fft_rows(const float2 *in, float2 *out, int N, int64_t nrows, int sign, const float2 *tw,
+                           hipStream_t s);
+// out[p][r][c] = in[p][c][r] / (sr[r] sc[c]) over `planes` N x N planes (sr NULL: no division)
+hipError_t launch_transpose_scale(const float2 *in, float2 *out, int N, int planes, const float *sr, const float *sc,
+                                  hipStream_t s);
+
 }  // namespace idg

@@ -157,3 +157,22 @@ def test_tuning_round_trip_and_validation():
         assert e.value.code == -1
     assert p.get_tuning()["adder_chunk"] == 17          # unchanged by the rejected calls
     assert p.get_tuning()["degrid_shape"] == "wide"
+
+
+def test_image_steps_validate_before_any_device_call():
+    # argument checks of idg_grid_to_image / idg_image_to_grid run on the host: fake addresses are
+    # never dereferenced when the call is rejected
+    L = ctypes.CDLL(idg.LIB_PATH)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    for fn in (L.idg_grid_to_image, L.idg_image_to_grid):
+        fn.argtypes = [vp, i32, vp, vp, vp, vp]
+        fn.restype = ctypes.c_int
+        a, b = vp(0x10000000), vp(0x90000000)
+        assert fn(a, 100, None, None, b, None) == -1            # not a power of two
+        assert fn(a, 32, None, None, b, None) == -1             # below 64
+        assert fn(a, 32768, None, None, b, None) == -1          # above 16384
+        assert fn(None, 256, None, None, b, None) == -1         # NULL input
+        assert fn(a, 256, vp(0x20000000), None, b, None) == -1  # one correction only
+        assert fn(a, 256, None, None, vp(0x10000000 + 4096), None) == -1   # overlapping buffers
+        L.idg_last_error.restype = ctypes.c_char_p
+        assert b"overlap" in L.idg_last_error()

@@ -1,0 +1,236 @@
+"""Master grid <-> image on the GPU against the float64 oracle.
+
+* whole transforms at small sizes (both directions, with and without the
+  correction), element by element;
+* the workload grid sizes (512, 4096, 8192): sampled pixels / cells that the
+  oracle computes one by one, plus the round trip image_to_grid(grid_to_image(g))
+  = N^2 g, which holds at any size;
+* the largest size (16384): the round trip;
+* the adjoint identity on the GPU's outputs;
+* the major cycle: model image -> grid -> degrid against the oracle's chain and
+  against the measurement equation of a point source.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import idg as oidg
+from oracle import image as oim
+from synth import pswf_taper_2d
+from tests.gpu_common import GRID_RMS_TOL, VIS_RMS_TOL, max_rel, require_gpu, rms_rel, say, to_dev
+from tests.util import make_mini, plan_of
+
+pytestmark = pytest.mark.gpu
+
+IMAGE_MAX_TOL = 1e-4      # per element, relative to the largest |value|
+
+
+def _rand_grid(rng, N):
+    re = rng.standard_normal((4, N, N), dtype=np.float32)
+    im = rng.standard_normal((4, N, N), dtype=np.float32)
+    return (re + 1j * im).astype(np.complex64)
+
+
+def _corr(rng, N):
+    return (0.5 + rng.random(N)).astype(np.float32), (0.5 + rng.random(N)).astype(np.float32)
+
+
+def _run(fn, src, cl, cm):
+    import torch
+    import paper_1909_07226_amd as idg
+    s = torch.from_numpy(src).cuda()
+    out = torch.empty_like(s)
+    tl = None if cl is None else torch.from_numpy(cl).cuda()
+    tm = None if cm is None else torch.from_numpy(cm).cuda()
+    getattr(idg, fn)(s, tl, tm, out)
+    idg.sync()
+    assert torch.equal(s.cpu(), torch.from_numpy(src)), "input changed"
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("N", [64, 128, 256, 512])
+@pytest.mark.parametrize("with_corr", [True, False])
+def test_whole_transforms_match_oracle(N, with_corr):
+    require_gpu()
+    rng = np.random.default_rng(100 + N)
+    g = _rand_grid(rng, N)
+    cl, cm = _corr(rng, N) if with_corr else (None, None)
+    ocl = np.ones(N) if cl is None else cl.astype(np.float64)
+    ocm = np.ones(N) if cm is None else cm.astype(np.float64)
+    say(f"[image] N={N} corr={with_corr}")
+    img = _run("grid_to_image", g, cl, cm)
+    ref = oim.grid_to_image(g, ocl, ocm)
+    say(f"    grid->image rms {rms_rel(img, ref):.2e} max {max_rel(img, ref):.2e}")
+    assert rms_rel(img, ref) < GRID_RMS_TOL and max_rel(img, ref) < IMAGE_MAX_TOL
+    back = _run("image_to_grid", g, cl, cm)
+    ref = oim.image_to_grid(g, ocl, ocm)
+    say(f"    image->grid rms {rms_rel(back, ref):.2e} max {max_rel(back, ref):.2e}")
+    assert rms_rel(back, ref) < GRID_RMS_TOL and max_rel(back, ref) < IMAGE_MAX_TOL
+
+
+def test_adjoint_identity_on_gpu():
+    require_gpu()
+    N = 1024
+    rng = np.random.default_rng(7)
+    g, im = _rand_grid(rng, N), _rand_grid(rng, N)
+    cl, cm = _corr(rng, N)
+    say(f"[image adjoint] N={N}")
+    tg = _run("grid_to_image", g, cl, cm).astype(np.complex128)
+    ti = _run("image_to_grid", im, cl, cm).astype(np.complex128)
+    lhs = np.vdot(ti, g.astype(np.complex128))
+    rhs = np.vdot(im.astype(np.complex128), tg)
+    say(f"    rel {abs(lhs - rhs) / abs(rhs):.2e}")
+    assert abs(lhs - rhs) / abs(rhs) < 1e-5
+
+
+def _round_trip_rel(g_dev):
+    import torch
+    import paper_1909_07226_amd as idg
+    N = g_dev.shape[-1]
+    img = torch.empty_like(g_dev)
+    idg.grid_to_image(g_dev, None, None, img)
+    back = torch.empty_like(g_dev)
+    idg.image_to_grid(img, None, None, back)
+    idg.sync()
+    del img
+    back.div_(float(N) * float(N))
+    back.sub_(g_dev)
+    return float(torch.linalg.vector_norm(back) / torch.linalg.vector_norm(g_dev))
+
+
+@pytest.mark.parametrize("N", [512, 4096, 8192])
+def test_workload_sizes_sampled_and_round_trip(N):
+    require_gpu()
+    import torch
+    import paper_1909_07226_amd as idg
+    rng = np.random.default_rng(200 + N.bit_length())
+    g = _rand_grid(rng, N)
+    cl, cm = _corr(rng, N)
+    xs = np.concatenate([[0, N - 1, N // 2], rng.integers(0, N, 5)])
+    ys = np.concatenate([[N - 1, 0, N // 2], rng.integers(0, N, 5)])
+    say(f"[image sampled] N={N} pixels {list(zip(xs.tolist(), ys.tolist()))}")
+    gd = torch.from_numpy(g).cuda()
+    tl, tm = torch.from_numpy(cl).cuda(), torch.from_numpy(cm).cuda()
+    out = torch.empty_like(gd)
+    idg.grid_to_image(gd, tl, tm, out)
+    idg.sync()
+    got = out[:, torch.from_numpy(ys).cuda(), torch.from_numpy(xs).cuda()].cpu().numpy()
+    ref = oim.grid_to_image_at(g, xs, ys, cl.astype(np.float64), cm.astype(np.float64))
+    # the sampled values' error is judged against the rms of the image (|value| ~ N sqrt(2) / corr)
+    scale = np.sqrt(2.0) * N
+    err = np.abs(got - ref).max() / scale
+    say(f"    grid->image sampled err {err:.2e}")
+    assert err < IMAGE_MAX_TOL
+    idg.image_to_grid(gd, tl, tm, out)
+    idg.sync()
+    got = out[:, torch.from_numpy(ys).cuda(), torch.from_numpy(xs).cuda()].cpu().numpy()
+    ref = oim.image_to_grid_at(g, xs, ys, cl.astype(np.float64), cm.astype(np.float64))
+    err = np.abs(got - ref).max() / (scale * np.abs(1.0 / cl).mean() * np.abs(1.0 / cm).mean())
+    say(f"    image->grid sampled err {err:.2e}")
+    assert err < IMAGE_MAX_TOL
+    del out
+    rel = _round_trip_rel(gd)
+    say(f"    round trip rel {rel:.2e}")
+    assert rel < GRID_RMS_TOL
+
+
+def test_largest_size_round_trip():
+    require_gpu()
+    import torch
+    N = 16384
+    say(f"[image round trip] N={N}")
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    gd = torch.randn((4, N, N), dtype=torch.complex64, device="cuda", generator=gen)
+    rel = _round_trip_rel(gd)
+    say(f"    round trip rel {rel:.2e}")
+    assert rel < GRID_RMS_TOL
+
+
+def _continuous_taper(L, beta, S, N):
+    from scipy.special import pro_ang1
+    alpha = beta * np.pi / 2
+    lx = (np.arange(N) - N // 2) * S / N
+    c = np.array([pro_ang1(0, 0, alpha, 2 * li / S)[0] if abs(2 * li / S) < 1 else 1.0 for li in lx])
+    return (L * c / pro_ang1(0, 0, alpha, 0.0)[0]).astype(np.float32), lx
+
+
+def _tracks(rng, nbl, nt, N):
+    uvw = np.zeros((nbl, nt, 3))
+    t = np.arange(nt)
+    for b in range(nbl):
+        start = rng.uniform(-N / 4, N / 4, 2)
+        vel = rng.uniform(-0.8, 0.8, 2)
+        uvw[b, :, 0] = start[0] + vel[0] * t
+        uvw[b, :, 1] = start[1] + vel[1] * t
+    return uvw
+
+
+def test_major_cycle_on_gpu():
+    # model image (point source) -> image_to_grid -> degrid against the oracle's chain and against
+    # the measurement equation; then grid -> grid_to_image against the oracle's dirty image
+    require_gpu()
+    import torch
+    import paper_1909_07226_amd as idg
+    N, L, beta, S = 128, 32, 7, 1.0
+    rng = np.random.default_rng(22)
+    uvw = _tracks(rng, 5, 30, N)
+    uvw[..., 2] = rng.uniform(-1.5, 1.5, (5, 1))
+    wl = make_mini(uvw, N=N, L=L, beta=beta, S=S, taper=pswf_taper_2d(L, beta))
+    oplan = plan_of(wl)
+    assert oplan.nr_dropped == 0
+    x0, y0 = N // 2 + 17, N // 2 - 11
+    model = np.zeros((4, N, N), np.complex64)
+    model[0, y0, x0] = model[3, y0, x0] = 1.0
+    corr, lx = _continuous_taper(L, beta, S, N)
+    say(f"[major cycle] N={N} L={L} source at ({x0}, {y0})")
+    # GPU chain
+    plan = idg.Plan.from_workload(wl)
+    d = to_dev(wl)
+    tc = torch.from_numpy(corr).cuda()
+    md = torch.from_numpy(model).cuda()
+    grid = torch.empty_like(md)
+    idg.image_to_grid(md, tc, tc, grid)
+    vis = torch.empty_like(d["vis"])
+    idg.degrid(plan, d["uvw"], d["freqs"], grid, d["aterms"], d["taper"], vis)
+    idg.sync()
+    v = vis.cpu().numpy()
+    # oracle chain
+    og = oim.image_to_grid(model, corr.astype(np.float64), corr.astype(np.float64))
+    assert rms_rel(grid.cpu().numpy(), og) < GRID_RMS_TOL
+    ov = oidg.degrid(oplan, wl.uvw, wl.freqs, og, wl.aterms, wl.taper)
+    say(f"    vis rms vs oracle chain {rms_rel(v, ov):.2e}")
+    assert rms_rel(v, ov) < VIS_RMS_TOL
+    l0, m0 = lx[x0], lx[y0]
+    n0 = np.sqrt(1.0 - l0 * l0 - m0 * m0) - 1.0
+    dme = np.exp(-2j * np.pi * (uvw[..., 0] * l0 + uvw[..., 1] * m0 + uvw[..., 2] * n0))
+    err = np.abs(v[..., 0, 0] - dme).max()
+    say(f"    vis vs measurement equation max {err:.2e}")
+    assert err < 1e-4 and np.abs(v[..., 0, 3] - dme).max() < 1e-4
+    # dirty image of the predicted visibilities
+    d["vis"] = vis
+    grid.zero_()
+    idg.grid(plan, d["uvw"], d["freqs"], d["vis"], d["aterms"], d["taper"], grid)
+    img = torch.empty_like(grid)
+    idg.grid_to_image(grid, tc, tc, img)
+    idg.sync()
+    g = grid.cpu().numpy()
+    og = oidg.grid(oplan, wl.uvw, wl.freqs, v, wl.aterms, wl.taper)
+    say(f"    grid rms vs oracle {rms_rel(g, og):.2e}")
+    assert rms_rel(g, og) < GRID_RMS_TOL
+    # near the edges the taper is ~1e-6 and dividing by it magnifies float32 rounding a millionfold:
+    # the transform of this very grid is compared everywhere with the division undone, the
+    # corrected images where the correction is well conditioned
+    c64 = corr.astype(np.float64)
+    im = img.cpu().numpy()
+    undone = im.astype(np.complex128) * np.outer(c64, c64)
+    assert rms_rel(undone, oim.grid_to_image(g, np.ones(N), np.ones(N))) < GRID_RMS_TOL
+    keep = np.abs(lx) <= 0.35 * S
+    box = np.ix_(range(4), keep, keep)
+    oimg = oim.grid_to_image(og, c64, c64)
+    say(f"    dirty image rms vs oracle (|l|, |m| <= 0.35) {rms_rel(im[box], oimg[box]):.2e}")
+    assert rms_rel(im[box], oimg[box]) < GRID_RMS_TOL
+    # inside the region where the correction is well conditioned, the dirty image peaks at the source
+    a = np.abs(im[0])
+    a[~keep, :] = 0
+    a[:, ~keep] = 0
+    assert np.unravel_index(a.argmax(), (N, N)) == (y0, x0)

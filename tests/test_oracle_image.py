@@ -116,3 +116,16 @@ def test_major_cycle_predicts_the_measurement_equation(w_scale):
     err = np.abs(vis[..., 0, 0] - dme).max()
     assert err < 1e-4, err
     assert np.abs(vis[..., 0, 1]).max() < 1e-12 and np.abs(vis[..., 0, 3] - dme).max() < 1e-4
+
+
+def test_one_pixel_forms_match_the_whole_transform():
+    # the per-pixel forms used on grids too large for the whole transform give the same values
+    N = 16
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal((4, N, N)) + 1j * rng.standard_normal((4, N, N))
+    cl, cm = 0.5 + rng.random(N), 0.5 + rng.random(N)
+    xs, ys = rng.integers(0, N, 7), rng.integers(0, N, 7)
+    full = oim.grid_to_image(g, cl, cm)
+    assert _rel(oim.grid_to_image_at(g, xs, ys, cl, cm), full[:, ys, xs]) < 1e-12
+    full = oim.image_to_grid(g, cl, cm)
+    assert _rel(oim.image_to_grid_at(g, xs, ys, cl, cm), full[:, ys, xs]) < 1e-12
