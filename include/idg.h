@@ -263,10 +263,12 @@ int idg_split_subgrids(idg_plan_t plan, const idg_cf32 *grid_d, int64_t first, i
  * corr[x] = L c(l_x) gives the division by L^2 c(l) c(m)).  Unnormalised.
  *   grid_d    device complex64 [4][N][N], read
  *   corr_l_d, corr_m_d  device float32 [N] (both NULL: no division)
- *   image_d   device complex64 [4][N][N], OVERWRITTEN; must not overlap grid_d
- * N = grid_size must be a power of two in [64, 16384].  Device scratch of
- * 4 N^2 x 8 bytes is allocated stream-ordered for the call.
- * Errors: IDG_EINVAL (size, NULL or overlapping buffers), IDG_ENOMEM, IDG_EHIP.
+ *   image_d   device complex64 [4][N][N], OVERWRITTEN; may be grid_d itself
+ *             (in place), must not overlap it otherwise
+ * N = grid_size must be a power of two in [64, 16384].  Two passes over the
+ * array; N/2 x 8 bytes of twiddles are allocated stream-ordered for the call.
+ * Errors: IDG_EINVAL (size, NULL or partly overlapping buffers), IDG_ENOMEM,
+ * IDG_EHIP.
  */
 int idg_grid_to_image(const idg_cf32 *grid_d, int32_t grid_size, const float *corr_l_d, const float *corr_m_d,
                       idg_cf32 *image_d, void *stream);

@@ -689,66 +689,38 @@ static int image_args(const char *fn, const void *src, int32_t N, const float *c
   if ((cl == nullptr) != (cm == nullptr)) return fail(IDG_EINVAL, "%s: give both corrections or neither", fn);
   const size_t bytes = size_t(4) * N * N * sizeof(idg_cf32);
   const char *a = static_cast<const char *>(src), *b = static_cast<const char *>(dst);
-  if (a < b + bytes && b < a + bytes) return fail(IDG_EINVAL, "%s: input and output overlap", fn);
+  if (a != b && a < b + bytes && b < a + bytes) return fail(IDG_EINVAL, "%s: input and output overlap partially", fn);
   return IDG_OK;
 }
 
-// Scratch for the image steps: [4][N][N] complex plus the N/2 twiddles.
-static int image_scratch(int N, hipStream_t s, float2 **buf, float2 **tw) {
-  const size_t n = size_t(4) * N * N;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(buf), (n + size_t(N) / 2) * sizeof(float2), s),
-          "image scratch allocation");
-  *tw = *buf + n;
-  hipError_t e = idg::launch_image_twiddles(*tw, N, s);
-  if (e != hipSuccess) {
-    (void)hipFreeAsync(*buf, s);
-    return hip_fail(e, "image twiddles");
-  }
+// The image steps: N/2 twiddles in stream-ordered scratch, two passes.
+static int image_transform(const char *fn, bool to_image, const idg_cf32 *src_d, int32_t N, const float *cl,
+                           const float *cm, idg_cf32 *dst_d, void *stream) {
+  int rc = image_args(fn, src_d, N, cl, cm, dst_d);
+  if (rc != IDG_OK) return rc;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  float2 *tw = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&tw), size_t(N) / 2 * sizeof(float2), s), "image twiddles");
+  const float2 *in = reinterpret_cast<const float2 *>(src_d);
+  float2 *out = reinterpret_cast<float2 *>(dst_d);
+  hipError_t e = idg::launch_image_twiddles(tw, N, s);
+  if (e == hipSuccess)
+    e = to_image ? idg::launch_grid_to_image(in, out, N, cl, cm, tw, s)
+                 : idg::launch_image_to_grid(in, out, N, cl, cm, tw, s);
+  const hipError_t ef = hipFreeAsync(tw, s);
+  if (e != hipSuccess) return hip_fail(e, to_image ? "idg_grid_to_image: launch" : "idg_image_to_grid: launch");
+  HIP_TRY(ef, "image twiddles release");
   return IDG_OK;
 }
 
 int idg_grid_to_image(const idg_cf32 *grid_d, int32_t grid_size, const float *corr_l_d, const float *corr_m_d,
                       idg_cf32 *image_d, void *stream) {
-  int rc = image_args("idg_grid_to_image", grid_d, grid_size, corr_l_d, corr_m_d, image_d);
-  if (rc != IDG_OK) return rc;
-  const int N = grid_size;
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  float2 *scr = nullptr, *tw = nullptr;
-  if ((rc = image_scratch(N, s, &scr, &tw)) != IDG_OK) return rc;
-  const float2 *g = reinterpret_cast<const float2 *>(grid_d);
-  float2 *img = reinterpret_cast<float2 *>(image_d);
-  // rows (along u) into image_d, transpose into scratch, rows (along v) in place, transpose back
-  // into image_d dividing by corr_m[y] corr_l[x]
-  hipError_t e = idg::launch_fft_rows(g, img, N, int64_t(4) * N, +1, tw, s);
-  if (e == hipSuccess) e = idg::launch_transpose_scale(img, scr, N, 4, nullptr, nullptr, s);
-  if (e == hipSuccess) e = idg::launch_fft_rows(scr, scr, N, int64_t(4) * N, +1, tw, s);
-  if (e == hipSuccess) e = idg::launch_transpose_scale(scr, img, N, 4, corr_m_d, corr_l_d, s);
-  const hipError_t ef = hipFreeAsync(scr, s);
-  if (e != hipSuccess) return hip_fail(e, "idg_grid_to_image: launch");
-  HIP_TRY(ef, "idg_grid_to_image: scratch release");
-  return IDG_OK;
+  return image_transform("idg_grid_to_image", true, grid_d, grid_size, corr_l_d, corr_m_d, image_d, stream);
 }
 
 int idg_image_to_grid(const idg_cf32 *image_d, int32_t grid_size, const float *corr_l_d, const float *corr_m_d,
                       idg_cf32 *grid_d, void *stream) {
-  int rc = image_args("idg_image_to_grid", image_d, grid_size, corr_l_d, corr_m_d, grid_d);
-  if (rc != IDG_OK) return rc;
-  const int N = grid_size;
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  float2 *scr = nullptr, *tw = nullptr;
-  if ((rc = image_scratch(N, s, &scr, &tw)) != IDG_OK) return rc;
-  const float2 *img = reinterpret_cast<const float2 *>(image_d);
-  float2 *g = reinterpret_cast<float2 *>(grid_d);
-  // transpose into scratch dividing by corr_m[y] corr_l[x] (scratch[x][y] = image[y][x] / ...),
-  // rows (along y) in place, transpose into grid_d, rows (along x) in place
-  hipError_t e = idg::launch_transpose_scale(img, scr, N, 4, corr_l_d, corr_m_d, s);
-  if (e == hipSuccess) e = idg::launch_fft_rows(scr, scr, N, int64_t(4) * N, -1, tw, s);
-  if (e == hipSuccess) e = idg::launch_transpose_scale(scr, g, N, 4, nullptr, nullptr, s);
-  if (e == hipSuccess) e = idg::launch_fft_rows(g, g, N, int64_t(4) * N, -1, tw, s);
-  const hipError_t ef = hipFreeAsync(scr, s);
-  if (e != hipSuccess) return hip_fail(e, "idg_image_to_grid: launch");
-  HIP_TRY(ef, "idg_image_to_grid: scratch release");
-  return IDG_OK;
+  return image_transform("idg_image_to_grid", false, image_d, grid_size, corr_l_d, corr_m_d, grid_d, stream);
 }
 
 int idg_subgrid_fft(idg_cf32 *data_d, int64_t count, int32_t subgrid_size, int32_t direction, void *stream) {

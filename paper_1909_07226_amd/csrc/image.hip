@@ -6,17 +6,25 @@
 //                 / (corr_m[y] corr_l[x])
 //
 // and its adjoint.  For N a power of two the centred 1-D transform is
-// (-1)^k FFT[(-1)^n x], done per row in LDS (radix-2, decimation in frequency,
-// natural order in, bit-reversed order out); the 2-D transform is rows, a tiled
-// transpose, rows again and a transpose back.  Every pass reads and writes the
-// 4 x N x N complex64 array once: HBM-bound.
+// (-1)^k FFT[(-1)^n x].  The 2-D transform is two passes over HBM: one over
+// rows (contiguous), one over blocks of C adjacent columns, each workgroup
+// holding whole transforms in LDS.  The column pass reads and writes C x 8
+// bytes per row; its blocks are mapped so that neighbours sharing cache lines
+// run on one XCD (one L2).  The division is fused into the column pass.
+//
+// Inside a workgroup: radix-2 decimation in frequency, three stages at a time
+// in registers (a closed set of 8 elements per work item), one LDS round trip
+// per three stages; the first three stages read HBM directly; the output is
+// un-bit-reversed on its way from LDS to HBM.
 #include "internal.h"
 
 #include <cmath>
 
 namespace idg {
 
-constexpr int kImgTile = 32;
+constexpr int kXcds = 8;
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
 
 // tw[m] = exp(-2 pi i m / N), m < N/2, from float64.
 __global__ void image_twiddle_kernel(float2 *tw, int N) {
@@ -27,86 +35,224 @@ __global__ void image_twiddle_kernel(float2 *tw, int N) {
   tw[m] = make_float2(float(c), float(-s));
 }
 
-template <int N>
-constexpr int fft_threads() {
-  return N / 2 < 512 ? N / 2 : 512;
+__device__ __forceinline__ float2 fmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-template <int N>
-__device__ __forceinline__ int bit_reverse_n(int i) {
-  return int(__brev(unsigned(i)) >> (32 - __builtin_ctz(N)));
+// a * exp(SIGN 2 pi i k / 8), k < 4 (constant after unrolling)
+template <int SIGN>
+__device__ __forceinline__ float2 mul_root8(float2 a, int k) {
+  constexpr float r = 0.70710678118654752440f;
+  constexpr float s = SIGN < 0 ? -1.0f : 1.0f;
+  switch (k) {
+    case 0: return a;
+    case 2: return SIGN < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);  // * (-+ i)
+    case 1: return fmul(a, make_float2(r, s * r));
+    default: return fmul(a, make_float2(-r, s * r));
+  }
 }
 
-// One centred transform of length N per row, rows [0, nrows): out may equal in
-// (each workgroup reads its whole row before it writes).  SIGN = +1: exp(+...).
-template <int N, int SIGN>
-__global__ void __launch_bounds__(fft_threads<N>()) fft_rows_kernel(const float2 *in, float2 *out,
-                                                                   const float2 *tw) {
-  constexpr int NT = fft_threads<N>();
-  __shared__ float2 s[N];
+// R radix-2 decimation-in-frequency stages (half-spans h_min 2^(R-1) down to
+// h_min) on the 2^R elements v[m] = x[i_b + m h_min] of one closed set, lo =
+// i_b mod h_min.  A stage of half-span h maps (x[i], x[i + h]) with i mod 2h < h
+// to (x[i] + x[i + h], (x[i] - x[i + h]) exp(SIGN 2 pi i (i mod h) / (2h))).
+template <int N, int R, int SIGN>
+__device__ __forceinline__ void dif_set(float2 (&v)[1 << R], int lo, int h_min, const float2 *__restrict__ tw) {
+#pragma unroll
+  for (int q = R - 1; q >= 0; --q) {
+    const int hq = h_min << q;
+    float2 base = tw[lo * (N / (2 * hq))];  // exp(-2 pi i lo / (2 hq))
+    if (SIGN > 0) base.y = -base.y;
+#pragma unroll
+    for (int m = 0; m < (1 << R); ++m) {
+      if (m & (1 << q)) continue;
+      const float2 a = v[m], b = v[m + (1 << q)];
+      v[m] = make_float2(a.x + b.x, a.y + b.y);
+      // (i mod hq) = lo + r h_min with r = m mod 2^q: the twiddle is base exp(SIGN 2 pi i r / 2^(q+1))
+      const float2 w = mul_root8<SIGN>(base, (m & ((1 << q) - 1)) << (2 - q));
+      v[m + (1 << q)] = fmul(make_float2(a.x - b.x, a.y - b.y), w);
+    }
+  }
+}
+
+// A workgroup holds C transforms of length N: rows (COLS false: element i of
+// transform c at row b0 + c, column i) or columns (COLS true: row i, column
+// b0 + c).  LDS indices are padded so that the strided patterns of the
+// butterflies and of the bit-reversed read-out spread over the banks.
+// threads of a workgroup holding `elems` elements: one per closed set of 8, at most 512
+constexpr int fft_threads(int elems) { return elems / 8 < 512 ? elems / 8 : 512; }
+
+template <int N, int C, bool COLS>
+struct FftShape {
+  static constexpr int n = ilog2c(N);
+  static constexpr int NT = fft_threads(N * C);
+  static constexpr int RSH = n > 8 ? n - 5 : 3;
+  static constexpr int ROW = N + (N >> 3) + (N >> RSH);
+  static constexpr int LDS = COLS ? C * (N + N / 8) : C * ROW;
+  static __device__ __forceinline__ int lds(int i, int c) {
+    if constexpr (COLS)
+      return C * (i + (i >> 3)) + c;
+    else
+      return c * ROW + i + (i >> 3) + (i >> RSH);
+  }
+};
+
+// Three (or fewer, at the end) stages from LDS to LDS; H is the largest half-span.
+template <int N, int C, bool COLS, int SIGN, int H, int R>
+__device__ __forceinline__ void lds_group(float2 *s, const float2 *__restrict__ tw, int tid) {
+  using S = FftShape<N, C, COLS>;
+  constexpr int E = 1 << R, HM = H >> (R - 1), NSET = N / E, PER = NSET * C / S::NT;
+  constexpr int LH = ilog2c(H), LHM = ilog2c(HM);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int w = tid + k * S::NT;
+    const int c = COLS ? w % C : w / NSET, set = COLS ? w / C : w % NSET;
+    const int lo = set & (HM - 1), ib = lo + ((set >> LHM) << (LH + 1));
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = s[S::lds(ib + m * HM, c)];
+    dif_set<N, R, SIGN>(v, lo, HM, tw);
+#pragma unroll
+    for (int m = 0; m < E; ++m) s[S::lds(ib + m * HM, c)] = v[m];
+  }
+  __syncthreads();
+}
+
+template <int N, int C, bool COLS, int SIGN, int H>
+__device__ __forceinline__ void lds_groups(float2 *s, const float2 *__restrict__ tw, int tid) {
+  if constexpr (H >= 4) {
+    lds_group<N, C, COLS, SIGN, H, 3>(s, tw, tid);
+    lds_groups<N, C, COLS, SIGN, H / 8>(s, tw, tid);
+  } else if constexpr (H == 2) {
+    lds_group<N, C, COLS, SIGN, 2, 2>(s, tw, tid);
+  } else if constexpr (H == 1) {
+    lds_group<N, C, COLS, SIGN, 1, 1>(s, tw, tid);
+  }
+}
+
+// Centred length-N transforms of 4 N^2 / (N C) workgroups of C rows or columns
+// of the [4][N][N] array; out may equal in (a workgroup reads all its elements
+// before its first write; workgroups are disjoint).  SCALE 1 divides the input
+// by sr[row] sc[col], SCALE 2 the output.
+template <int N, int C, bool COLS, int SIGN, int SCALE>
+__global__ void __launch_bounds__(fft_threads(N * C))
+    fft_batch_kernel(const float2 *in, float2 *out, const float2 *__restrict__ tw, const float *__restrict__ sr,
+                     const float *__restrict__ sc) {
+  using S = FftShape<N, C, COLS>;
+  constexpr int NT = S::NT, n = S::n;
+  __shared__ float2 s[S::LDS];
+  // workgroup i runs on XCD i mod 8: give each XCD a contiguous range of blocks
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int lb = (nb % kXcds == 0) ? (bid % kXcds) * (nb / kXcds) + bid / kXcds : bid;
+  constexpr int per_plane = N / C;
+  const int b0 = (lb % per_plane) * C;
+  const int64_t pbase = int64_t(lb / per_plane) * N * N;
   const int tid = threadIdx.x;
-  const int64_t base = int64_t(blockIdx.x) * N;
-  for (int i = tid; i < N; i += NT) {
-    const float2 v = in[base + i];
-    s[i] = (i & 1) ? make_float2(-v.x, -v.y) : v;
-  }
-  __syncthreads();
-  // decimation in frequency: a stage of span 2h combines s[i0] and s[i0 + h]
-  for (int h = N / 2; h >= 1; h >>= 1) {
-    const int tstride = N / (2 * h);  // twiddle index step: exp(-+2 pi i j / (2h)) = tw[j * N / (2h)]
-    for (int b = tid; b < N / 2; b += NT) {
-      const int j = b & (h - 1);
-      const int i0 = ((b - j) << 1) + j, i1 = i0 + h;
-      const float2 a = s[i0], c = s[i1];
-      float2 w = tw[j * tstride];
-      if (SIGN > 0) w.y = -w.y;
-      const float2 d = make_float2(a.x - c.x, a.y - c.y);
-      s[i0] = make_float2(a.x + c.x, a.y + c.y);
-      s[i1] = make_float2(d.x * w.x - d.y * w.y, d.x * w.y + d.y * w.x);
-    }
-    __syncthreads();
-  }
-  for (int k = tid; k < N; k += NT) {
-    const float2 v = s[bit_reverse_n<N>(k)];
-    out[base + k] = (k & 1) ? make_float2(-v.x, -v.y) : v;
-  }
-}
+  auto gofs = [&](int i, int c) -> int64_t {
+    return COLS ? pbase + int64_t(i) * N + b0 + c : pbase + int64_t(b0 + c) * N + i;
+  };
+  auto inv_corr = [&](int i, int c) -> float {
+    return COLS ? 1.0f / (sr[i] * sc[b0 + c]) : 1.0f / (sr[b0 + c] * sc[i]);
+  };
 
-// out[p][r][c] = in[p][c][r] / (sr[r] sc[c]) (no division when sr is NULL), N x N
-// planes, tiles of 32 x 32 through LDS.  Grid (N/32, N/32, planes).
-__global__ void __launch_bounds__(256) transpose_scale_kernel(const float2 *in, float2 *out, int N,
-                                                              const float *sr, const float *sc) {
-  __shared__ float2 t[kImgTile][kImgTile + 1];
-  const int64_t plane = int64_t(blockIdx.z) * N * N;
-  const int bx = blockIdx.x * kImgTile, by = blockIdx.y * kImgTile;  // tile of `in`: rows by.., cols bx..
-  const int tx = threadIdx.x % kImgTile, ty = threadIdx.x / kImgTile;
-  for (int r = ty; r < kImgTile; r += 256 / kImgTile) t[r][tx] = in[plane + int64_t(by + r) * N + bx + tx];
-  __syncthreads();
-  for (int r = ty; r < kImgTile; r += 256 / kImgTile) {
-    const int orow = bx + r, ocol = by + tx;  // out[orow][ocol] = in[ocol][orow]
-    float2 v = t[tx][r];
-    if (sr) {
-      const float f = 1.0f / (sr[orow] * sc[ocol]);
-      v = make_float2(v.x * f, v.y * f);
+  // stages of half-span N/2, N/4, N/8 straight from HBM: loads first, for bytes in flight
+  {
+    constexpr int HM = N / 8, PER = HM * C / NT;
+    float2 v[PER][8];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int w = tid + k * NT;
+      const int c = COLS ? w % C : w / HM, lo = COLS ? w / C : w % HM;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) v[k][m] = in[gofs(lo + m * HM, c)];
     }
-    out[plane + int64_t(orow) * N + ocol] = v;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int w = tid + k * NT;
+      const int c = COLS ? w % C : w / HM, lo = COLS ? w / C : w % HM;
+      const float sg = (lo & 1) ? -1.0f : 1.0f;  // (-1)^i; i = lo + m N/8 has the parity of lo
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        float f = sg;
+        if constexpr (SCALE == 1) f *= inv_corr(lo + m * HM, c);
+        v[k][m] = make_float2(v[k][m].x * f, v[k][m].y * f);
+      }
+      dif_set<N, 3, SIGN>(v[k], lo, HM, tw);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) s[S::lds(lo + m * HM, c)] = v[k][m];
+    }
+  }
+  __syncthreads();
+  lds_groups<N, C, COLS, SIGN, N / 16>(s, tw, tid);
+
+  // element i of LDS holds output k = bitreverse(i); times (-1)^k
+  constexpr int PER = N * C / NT;
+#pragma unroll 8
+  for (int k = 0; k < PER; ++k) {
+    const int w = tid + k * NT;
+    int i, kk, c;
+    if constexpr (COLS) {  // LDS order: each row of the output is still C x 8 contiguous bytes
+      c = w % C;
+      i = w / C;
+      kk = int(__brev(unsigned(i)) >> (32 - n));
+    } else {               // output order, contiguous along the row
+      c = w / N;
+      kk = w % N;
+      i = int(__brev(unsigned(kk)) >> (32 - n));
+    }
+    float2 v = s[S::lds(i, c)];
+    float f = (kk & 1) ? -1.0f : 1.0f;
+    if constexpr (SCALE == 2) f *= inv_corr(kk, c);
+    out[gofs(kk, c)] = make_float2(v.x * f, v.y * f);
   }
 }
 
 bool image_size_supported(int N) { return N >= 64 && N <= 16384 && (N & (N - 1)) == 0; }
 
-#define IDG_DISPATCH_N(N, EXPR)                            \
-  switch (N) {                                             \
-    case 64: { constexpr int NN = 64; EXPR; break; }       \
-    case 128: { constexpr int NN = 128; EXPR; break; }     \
-    case 256: { constexpr int NN = 256; EXPR; break; }     \
-    case 512: { constexpr int NN = 512; EXPR; break; }     \
-    case 1024: { constexpr int NN = 1024; EXPR; break; }   \
-    case 2048: { constexpr int NN = 2048; EXPR; break; }   \
-    case 4096: { constexpr int NN = 4096; EXPR; break; }   \
-    case 8192: { constexpr int NN = 8192; EXPR; break; }   \
-    case 16384: { constexpr int NN = 16384; EXPR; break; } \
-    default: return hipErrorInvalidValue;                  \
+// Elements per workgroup: rows, at least kRowElems (whole rows); columns, at
+// most kColElems (16384 x 9/8 x 8 bytes = 144 KiB of LDS: one workgroup per CU,
+// C = 16384 / N adjacent columns, up to 16 = one 128-byte line per row).
+#ifndef IDG_IMAGE_ROW_ELEMS
+#define IDG_IMAGE_ROW_ELEMS 2048
+#endif
+#ifndef IDG_IMAGE_COL_ELEMS
+#define IDG_IMAGE_COL_ELEMS 16384
+#endif
+constexpr int kRowElems = IDG_IMAGE_ROW_ELEMS, kColElems = IDG_IMAGE_COL_ELEMS;
+
+template <int N>
+constexpr int row_batch() {
+  return N >= kRowElems ? 1 : kRowElems / N;
+}
+template <int N>
+constexpr int col_batch() {
+  return kColElems / N < 1 ? 1 : (kColElems / N < 16 ? kColElems / N : 16);
+}
+
+template <int N, bool COLS, int SIGN, int SCALE>
+static hipError_t launch_fft_batch(const float2 *in, float2 *out, const float2 *tw, const float *sr, const float *sc,
+                                   hipStream_t st) {
+  constexpr int C = COLS ? col_batch<N>() : row_batch<N>();
+  using S = FftShape<N, C, COLS>;
+  static_assert(S::LDS * sizeof(float2) <= 160 * 1024, "LDS");
+  static_assert((N / 8) * C % S::NT == 0 && (N / 2) * C % S::NT == 0, "work split");
+  hipLaunchKernelGGL((fft_batch_kernel<N, C, COLS, SIGN, SCALE>), dim3(4 * N / C), dim3(S::NT), 0, st, in, out, tw,
+                     sr, sc);
+  return hipGetLastError();
+}
+
+#define IDG_DISPATCH_N(N, ...)                                    \
+  switch (N) {                                                    \
+    case 64: { constexpr int NN = 64; __VA_ARGS__; break; }       \
+    case 128: { constexpr int NN = 128; __VA_ARGS__; break; }     \
+    case 256: { constexpr int NN = 256; __VA_ARGS__; break; }     \
+    case 512: { constexpr int NN = 512; __VA_ARGS__; break; }     \
+    case 1024: { constexpr int NN = 1024; __VA_ARGS__; break; }   \
+    case 2048: { constexpr int NN = 2048; __VA_ARGS__; break; }   \
+    case 4096: { constexpr int NN = 4096; __VA_ARGS__; break; }   \
+    case 8192: { constexpr int NN = 8192; __VA_ARGS__; break; }   \
+    case 16384: { constexpr int NN = 16384; __VA_ARGS__; break; } \
+    default: return hipErrorInvalidValue;                         \
   }
 
 hipError_t launch_image_twiddles(float2 *tw, int N, hipStream_t s) {
@@ -115,25 +261,27 @@ hipError_t launch_image_twiddles(float2 *tw, int N, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_fft_rows(const float2 *in, float2 *out, int N, int64_t nrows, int sign, const float2 *tw,
-                           hipStream_t s) {
-  if (!image_size_supported(N) || nrows <= 0 || nrows > INT32_MAX) return hipErrorInvalidValue;
+hipError_t launch_grid_to_image(const float2 *grid, float2 *image, int N, const float *corr_l, const float *corr_m,
+                                const float2 *tw, hipStream_t s) {
+  hipError_t e = hipSuccess;
   IDG_DISPATCH_N(N, {
-    if (sign > 0)
-      hipLaunchKernelGGL((fft_rows_kernel<NN, 1>), dim3(unsigned(nrows)), dim3(fft_threads<NN>()), 0, s, in, out, tw);
-    else
-      hipLaunchKernelGGL((fft_rows_kernel<NN, -1>), dim3(unsigned(nrows)), dim3(fft_threads<NN>()), 0, s, in, out,
-                         tw);
+    e = launch_fft_batch<NN, false, 1, 0>(grid, image, tw, nullptr, nullptr, s);
+    if (e == hipSuccess)
+      e = corr_l ? launch_fft_batch<NN, true, 1, 2>(image, image, tw, corr_m, corr_l, s)
+                 : launch_fft_batch<NN, true, 1, 0>(image, image, tw, nullptr, nullptr, s);
   });
-  return hipGetLastError();
+  return e;
 }
 
-hipError_t launch_transpose_scale(const float2 *in, float2 *out, int N, int planes, const float *sr, const float *sc,
-                                  hipStream_t s) {
-  if (!image_size_supported(N) || planes <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(transpose_scale_kernel, dim3(N / kImgTile, N / kImgTile, planes), dim3(256), 0, s, in, out, N,
-                     sr, sc);
-  return hipGetLastError();
+hipError_t launch_image_to_grid(const float2 *image, float2 *grid, int N, const float *corr_l, const float *corr_m,
+                                const float2 *tw, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  IDG_DISPATCH_N(N, {
+    e = corr_l ? launch_fft_batch<NN, true, -1, 1>(image, grid, tw, corr_m, corr_l, s)
+               : launch_fft_batch<NN, true, -1, 0>(image, grid, tw, nullptr, nullptr, s);
+    if (e == hipSuccess) e = launch_fft_batch<NN, false, -1, 0>(grid, grid, tw, nullptr, nullptr, s);
+  });
+  return e;
 }
 
 }  // namespace idg

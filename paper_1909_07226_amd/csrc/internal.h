@@ -89,11 +89,12 @@ hipError_t launch_zero_samples(const int64_t *ids, int64_t n, float2 *vis, hipSt
 // master grid <-> image (image.hip)
 bool image_size_supported(int N);
 hipError_t launch_image_twiddles(float2 *tw, int N, hipStream_t s);
-// centred length-N transform of each of nrows contiguous rows (out may equal in); sign +1: exp(+...)
-hipError_t launch_fft_rows(const float2 *in, float2 *out, int N, int64_t nrows, int sign, const float2 *tw,
-                           hipStream_t s);
-// out[p][r][c] = in[p][c][r] / (sr[r] sc[c]) over `planes` N x N planes (sr NULL: no division)
-hipError_t launch_transpose_scale(const float2 *in, float2 *out, int N, int planes, const float *sr, const float *sc,
-                                  hipStream_t s);
+// the two-pass 2-D transforms of the [4][N][N] array (image.hip), N a power of two in [64, 16384]:
+// image = T(grid) / (corr_m[y] corr_l[x]), grid = T^H(image / (corr_m[y] corr_l[x])); corrections both
+// NULL or both set; in place allowed (image == grid); tw from launch_image_twiddles
+hipError_t launch_grid_to_image(const float2 *grid, float2 *image, int N, const float *corr_l, const float *corr_m,
+                                const float2 *tw, hipStream_t s);
+hipError_t launch_image_to_grid(const float2 *image, float2 *grid, int N, const float *corr_l, const float *corr_m,
+                                const float2 *tw, hipStream_t s);
 
 }  // namespace idg

@@ -234,3 +234,21 @@ def test_major_cycle_on_gpu():
     a[~keep, :] = 0
     a[:, ~keep] = 0
     assert np.unravel_index(a.argmax(), (N, N)) == (y0, x0)
+
+
+@pytest.mark.parametrize("N", [256, 4096])
+def test_in_place_equals_out_of_place(N):
+    require_gpu()
+    import torch
+    import paper_1909_07226_amd as idg
+    rng = np.random.default_rng(300 + N.bit_length())
+    g = torch.from_numpy(_rand_grid(rng, N)).cuda()
+    cl, cm = (torch.from_numpy(a).cuda() for a in _corr(rng, N))
+    say(f"[image in place] N={N}")
+    for fn in (idg.grid_to_image, idg.image_to_grid):
+        out = torch.empty_like(g)
+        fn(g, cl, cm, out)
+        work = g.clone()
+        fn(work, cl, cm, work)
+        idg.sync()
+        assert torch.equal(work, out)
