@@ -51,3 +51,123 @@ def classical_aliasing(beta, n=64, dps=40):
         evals, _ = mp.eigsy(m)
         lam0 = max(evals)
         return float(mp.sqrt(1 - lam0))
+
+
+# ---------------------------------------------------------------------------
+# The optimal window of image domain gridding (§4.3 and Appendix A).
+#
+# Index units: subgrid pixel k sits at x = k (k = 0 .. L-1), the imaged field
+# (the main lobe) is [0, L), the side lobes are x < 0 and x >= L.  A sample
+# shifted by s uv pixels from the subgrid centre sees the effective window
+#     f(x, s) = sum_k a_k sinc(x - k) exp(2 pi i (k - x) s / L)          (§4.2)
+# and the cost is the side-lobe energy averaged over the allowed shifts
+# |s| <= (L - beta + 1) / 2 (§4.3):
+#     eps^2 = a^T Rbar a,  Rbar = Qbar o Sbar  (elementwise),
+#     Qbar_kl = (int_{-inf}^0 + int_L^inf) sinc(x - k) sinc(x - l) dx,
+#     Sbar_kl = sinc((k - l)(L - beta + 1) / L)  (the mean of exp(2 pi i (k - l) s / L)).
+# With a^T a = 1 the total energy is 1 (the shifted sincs are orthonormal), so
+# the smallest eigenvalue of Rbar is eps^2 and its eigenvector the optimal a.
+#
+# Closed forms of the tail integrals (the appendix's antiderivative, with the
+# standard Ci(x) = -int_x^inf cos t / t dt):
+#   k != l: sinc(x-k) sinc(x-l) = (-1)^(k+l) sin^2(pi x) / (pi^2 (k-l)) [1/(x-k) - 1/(x-l)],
+#           int sin^2(pi y) / y dy = G(y) = (ln|y| - Ci(2 pi |y|)) / 2, G(0) = -(gamma + ln 2 pi) / 2;
+#   k == l: int sinc^2(y) dy = H(y) = -sin^2(pi y) / (pi^2 y) + Si(2 pi y) / pi,
+#           so the two tails give 1 - (Si(2 pi k) + Si(2 pi (L - k))) / pi.
+# ---------------------------------------------------------------------------
+
+
+def shift_half_range(L, beta):
+    """Largest |s| (uv pixels) a sample may sit from its subgrid centre before the main lobe wraps (§4.3)."""
+    return (L - beta + 1) / 2
+
+
+def _si_ci(x, dps):
+    """(Si(x), Ci(x)) for x > 0: scipy in float64 (dps None), mpmath otherwise."""
+    if dps is None:
+        from scipy.special import sici
+        s, c = sici(float(x))
+        return float(s), float(c)
+    return mp.si(x), mp.ci(x)
+
+
+def idg_window_matrix(L, beta, dps=None):
+    """Rbar (L x L, symmetric): numpy float64 when dps is None, else an mpmath matrix at dps digits."""
+    hi = dps is not None
+    ctx = mp.workdps(dps) if hi else None
+    if ctx:
+        ctx.__enter__()
+    try:
+        pi = mp.pi if hi else np.pi
+        one = mp.mpf(1) if hi else 1.0
+        si_tab, ci_tab = {}, {}
+        for m in range(1, L + 1):
+            si_tab[m], ci_tab[m] = _si_ci(2 * pi * m, dps)
+        g0 = -(mp.euler + mp.log(2 * pi)) / 2 if hi else -(np.euler_gamma + np.log(2 * np.pi)) / 2
+
+        def G(y):                   # y a nonnegative integer here
+            if y == 0:
+                return g0
+            return ((mp.log(y) if hi else np.log(y)) - ci_tab[y]) / 2
+
+        def si(m):
+            return 0 if m == 0 else si_tab[m]
+
+        R = mp.matrix(L, L) if hi else np.zeros((L, L))
+        w = 2 * shift_half_range(L, beta) * one / L
+        for k in range(L):
+            for l in range(L):
+                if k == l:
+                    q = 1 - (si(k) + si(L - k)) / pi
+                    s = one
+                else:
+                    q = (-1) ** (k + l) / (pi * pi * (k - l)) * ((G(k) - G(l)) - (G(L - k) - G(L - l)))
+                    d = (k - l) * w
+                    s = (mp.sin(pi * d) / (pi * d)) if hi else np.sinc(d)
+                R[k, l] = q * s
+        return R
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+
+
+def idg_optimal_window(L, beta, dps=None):
+    """(eps, a): eps = sqrt(smallest eigenvalue of Rbar), a its eigenvector (float64, a[L/2] = 1)."""
+    R = idg_window_matrix(L, beta, dps)
+    if dps is None:
+        lam, vec = np.linalg.eigh(R)
+        lam0, a = lam[0], vec[:, 0]
+    else:
+        with mp.workdps(dps):
+            lam, vec = mp.eigsy(R)
+            i0 = min(range(L), key=lambda i: lam[i])
+            lam0 = lam[i0]
+            a = np.array([float(vec[k, i0]) for k in range(L)])
+    a = a / a[L // 2]
+    return float(mp.sqrt(max(lam0, 0))) if dps is not None else float(np.sqrt(max(lam0, 0.0))), a
+
+
+def idg_window_error(a, L, beta):
+    """eps of an arbitrary taper a (float64): sqrt(a^T Rbar a / a^T a)."""
+    a = np.asarray(a, np.float64)
+    return float(np.sqrt(a @ idg_window_matrix(L, beta) @ a / (a @ a)))
+
+
+def rms_window(a, beta, x):
+    """The effective window's rms over the allowed shifts, at index-unit positions x (§4.2, §4.3):
+    sqrt(mean_s |f(x, s)|^2) = sqrt(sum_kl a_k a_l sinc(x - k) sinc(x - l) Sbar_kl)."""
+    a = np.asarray(a, np.float64)
+    L = a.size
+    k = np.arange(L)
+    d = np.subtract.outer(k, k)
+    sbar = np.sinc(d * 2 * shift_half_range(L, beta) / L)
+    x = np.atleast_1d(np.asarray(x, np.float64))
+    v = np.sinc(x[:, None] - k[None, :]) * a[None, :]          # [nx, L]
+    return np.sqrt(np.einsum("xk,kl,xl->x", v, sbar, v))
+
+
+def taper_correction(a, beta, N):
+    """Correction for the master-grid image steps: corr[X] = L rms_window(L X / N), X = 0 .. N-1
+    (image pixel X at l = (X - N/2) S / N is at index-unit position L X / N of a subgrid)."""
+    L = np.asarray(a).size
+    return L * rms_window(a, beta, L * np.arange(N) / N)
