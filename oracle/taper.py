@@ -61,10 +61,10 @@ def classical_aliasing(beta, n=64, dps=40):
 # shifted by s uv pixels from the subgrid centre sees the effective window
 #     f(x, s) = sum_k a_k sinc(x - k) exp(2 pi i (k - x) s / L)          (§4.2)
 # and the cost is the side-lobe energy averaged over the allowed shifts
-# |s| <= (L - beta + 1) / 2 (§4.3):
+# |s| <= h (§4.3; Table 1 is computed with h = (L - beta + 1)/2):
 #     eps^2 = a^T Rbar a,  Rbar = Qbar o Sbar  (elementwise),
 #     Qbar_kl = (int_{-inf}^0 + int_L^inf) sinc(x - k) sinc(x - l) dx,
-#     Sbar_kl = sinc((k - l)(L - beta + 1) / L)  (the mean of exp(2 pi i (k - l) s / L)).
+#     Sbar_kl = sinc(2 h (k - l) / L)  (the mean of exp(2 pi i (k - l) s / L) over |s| <= h).
 # With a^T a = 1 the total energy is 1 (the shifted sincs are orthonormal), so
 # the smallest eigenvalue of Rbar is eps^2 and its eigenvector the optimal a.
 #
@@ -78,7 +78,7 @@ def classical_aliasing(beta, n=64, dps=40):
 
 
 def shift_half_range(L, beta):
-    """Largest |s| (uv pixels) a sample may sit from its subgrid centre before the main lobe wraps (§4.3)."""
+    """The shift bound of Table 1 for kernel width beta: (L - beta + 1)/2 uv pixels (§4.3)."""
     return (L - beta + 1) / 2
 
 
@@ -91,8 +91,9 @@ def _si_ci(x, dps):
     return mp.si(x), mp.ci(x)
 
 
-def idg_window_matrix(L, beta, dps=None):
-    """Rbar (L x L, symmetric): numpy float64 when dps is None, else an mpmath matrix at dps digits."""
+def idg_window_matrix(L, max_shift, dps=None):
+    """Rbar (L x L, symmetric) for shifts |s| <= max_shift: numpy float64 when dps is None, else an
+    mpmath matrix at dps digits."""
     hi = dps is not None
     ctx = mp.workdps(dps) if hi else None
     if ctx:
@@ -114,7 +115,7 @@ def idg_window_matrix(L, beta, dps=None):
             return 0 if m == 0 else si_tab[m]
 
         R = mp.matrix(L, L) if hi else np.zeros((L, L))
-        w = 2 * shift_half_range(L, beta) * one / L
+        w = 2 * (mp.mpf(max_shift) if hi else float(max_shift)) / L
         for k in range(L):
             for l in range(L):
                 if k == l:
@@ -131,9 +132,9 @@ def idg_window_matrix(L, beta, dps=None):
             ctx.__exit__(None, None, None)
 
 
-def idg_optimal_window(L, beta, dps=None):
+def idg_optimal_window(L, max_shift, dps=None):
     """(eps, a): eps = sqrt(smallest eigenvalue of Rbar), a its eigenvector (float64, a[L/2] = 1)."""
-    R = idg_window_matrix(L, beta, dps)
+    R = idg_window_matrix(L, max_shift, dps)
     if dps is None:
         lam, vec = np.linalg.eigh(R)
         lam0, a = lam[0], vec[:, 0]
@@ -147,27 +148,27 @@ def idg_optimal_window(L, beta, dps=None):
     return float(mp.sqrt(max(lam0, 0))) if dps is not None else float(np.sqrt(max(lam0, 0.0))), a
 
 
-def idg_window_error(a, L, beta):
+def idg_window_error(a, max_shift):
     """eps of an arbitrary taper a (float64): sqrt(a^T Rbar a / a^T a)."""
     a = np.asarray(a, np.float64)
-    return float(np.sqrt(a @ idg_window_matrix(L, beta) @ a / (a @ a)))
+    return float(np.sqrt(a @ idg_window_matrix(a.size, max_shift) @ a / (a @ a)))
 
 
-def rms_window(a, beta, x):
+def rms_window(a, max_shift, x):
     """The effective window's rms over the allowed shifts, at index-unit positions x (§4.2, §4.3):
     sqrt(mean_s |f(x, s)|^2) = sqrt(sum_kl a_k a_l sinc(x - k) sinc(x - l) Sbar_kl)."""
     a = np.asarray(a, np.float64)
     L = a.size
     k = np.arange(L)
     d = np.subtract.outer(k, k)
-    sbar = np.sinc(d * 2 * shift_half_range(L, beta) / L)
+    sbar = np.sinc(d * 2 * max_shift / L)
     x = np.atleast_1d(np.asarray(x, np.float64))
     v = np.sinc(x[:, None] - k[None, :]) * a[None, :]          # [nx, L]
     return np.sqrt(np.einsum("xk,kl,xl->x", v, sbar, v))
 
 
-def taper_correction(a, beta, N):
+def taper_correction(a, max_shift, N):
     """Correction for the master-grid image steps: corr[X] = L rms_window(L X / N), X = 0 .. N-1
     (image pixel X at l = (X - N/2) S / N is at index-unit position L X / N of a subgrid)."""
     L = np.asarray(a).size
-    return L * rms_window(a, beta, L * np.arange(N) / N)
+    return L * rms_window(a, max_shift, L * np.arange(N) / N)

@@ -10,6 +10,9 @@
 * the rms window: equal to |a_k| at the samples, to the numerical rms over the
   shifts elsewhere, and to L c(l) of the continuous PSWF for the PSWF taper.
 
+The functions take the shift bound h (uv pixels) itself; Table 1 uses
+h = (L - beta + 1)/2 (shift_half_range).
+
 Table 1 is reproduced within 15 %, always from below.  The error is very
 sensitive to the shift bound: the table's values correspond to half-ranges
 0.007 - 0.06 pixel wider than (L - beta + 1)/2.  The readings of the
@@ -47,7 +50,7 @@ def test_window_matrix_against_quadrature(L, beta):
     s, ws = _gl(-h, h, step=0.25, order=16)
     d = np.subtract.outer(k, k)
     sbar = np.einsum("s,skl->kl", ws, np.cos(2 * np.pi * d[None] * s[:, None, None] / L)) / (2 * h)
-    R = ot.idg_window_matrix(L, beta)
+    R = ot.idg_window_matrix(L, h)
     assert np.abs(R - qbar * sbar).max() < 1e-12
     assert np.allclose(R, R.T, atol=0)
 
@@ -77,19 +80,21 @@ def test_error_is_the_side_lobe_energy(L, beta):
     rng = np.random.default_rng(L + beta)
     a = rng.standard_normal(L)
     a /= np.linalg.norm(a)
-    R = ot.idg_window_matrix(L, beta)
+    h = ot.shift_half_range(L, beta)
+    R = ot.idg_window_matrix(L, h)
     assert abs(a @ R @ a / _side_lobe_energy_brute_force(a, beta) - 1) < 1e-4
-    eps, aopt = ot.idg_optimal_window(L, beta)
+    eps, aopt = ot.idg_optimal_window(L, h)
     aopt = aopt / np.linalg.norm(aopt)
     assert abs(eps ** 2 / _side_lobe_energy_brute_force(aopt, beta) - 1) < 1e-3
 
 
 @pytest.mark.parametrize("L,beta", [(8, 3), (16, 5), (16, 7), (32, 7), (32, 9), (64, 7)])
 def test_optimal_window_beats_the_sampled_pswf(L, beta):
-    eps, a = ot.idg_optimal_window(L, beta)
-    eps_pswf = ot.idg_window_error(pswf_taper_1d(L, beta), L, beta)
+    h = ot.shift_half_range(L, beta)
+    eps, a = ot.idg_optimal_window(L, h)
+    eps_pswf = ot.idg_window_error(pswf_taper_1d(L, beta), h)
     assert eps < eps_pswf
-    assert abs(ot.idg_window_error(a, L, beta) / eps - 1) < 1e-6
+    assert abs(ot.idg_window_error(a, h) / eps - 1) < 1e-6
 
 
 def _table1_idg():
@@ -100,37 +105,37 @@ def _table1_idg():
 
 @pytest.mark.parametrize("beta,L,eps_paper", [r for r in _table1_idg() if r[0] <= 9])
 def test_table1_idg_columns_float64(beta, L, eps_paper):
-    eps, _ = ot.idg_optimal_window(L, beta)
+    eps, _ = ot.idg_optimal_window(L, ot.shift_half_range(L, beta))
     assert -0.15 < eps / eps_paper - 1 < 0.0
 
 
 @pytest.mark.parametrize("beta,L,eps_paper", [r for r in _table1_idg() if r[0] >= 11 and r[1] == 16])
 def test_table1_idg_columns_high_precision(beta, L, eps_paper):
     # eps^2 below ~1e-13 is beyond float64: Rbar and its eigenproblem in mpmath at 40 digits
-    eps, _ = ot.idg_optimal_window(L, beta, dps=40)
+    eps, _ = ot.idg_optimal_window(L, ot.shift_half_range(L, beta), dps=40)
     assert -0.15 < eps / eps_paper - 1 < 0.0
 
 
 def test_rms_window():
     L, beta = 16, 7
-    eps, a = ot.idg_optimal_window(L, beta)
+    h = ot.shift_half_range(L, beta)
+    eps, a = ot.idg_optimal_window(L, h)
     k = np.arange(L)
-    assert np.allclose(ot.rms_window(a, beta, k.astype(float)), np.abs(a), rtol=1e-13, atol=1e-15)
+    assert np.allclose(ot.rms_window(a, h, k.astype(float)), np.abs(a), rtol=1e-13, atol=1e-15)
     # elsewhere: the numerical rms of f(x, s) over the allowed shifts
     x = np.array([0.37, 3.5, 7.93, 12.25, 15.6])
-    h = ot.shift_half_range(L, beta)
     s, ws = _gl(-h, h, step=0.25, order=16)
     f = np.sum(a[None, None, :] * np.sinc(x[:, None, None] - k[None, None, :])
                * np.exp(2j * np.pi * (k[None, None, :] - x[:, None, None]) * s[None, :, None] / L), axis=-1)
     rms = np.sqrt((np.abs(f) ** 2) @ ws / (2 * h))
-    assert np.allclose(ot.rms_window(a, beta, x), rms, rtol=1e-12)
+    assert np.allclose(ot.rms_window(a, h, x), rms, rtol=1e-12)
 
 
 def test_pswf_correction_matches_the_continuous_window():
     # for the sampled PSWF taper the rms window is the continuous PSWF (up to the aliasing level)
     L, beta, N = 32, 7, 256
     a = pswf_taper_1d(L, beta)
-    corr = ot.taper_correction(a, beta, N)
+    corr = ot.taper_correction(a, ot.shift_half_range(L, beta), N)
     xn = np.arange(N) / N - 0.5                             # l / S of the master-grid pixels
     keep = np.abs(xn) <= 0.4
     cont = L * pswf_psi0(beta, 2 * xn[keep])
@@ -174,14 +179,13 @@ def _largest_eigenvector(mp):
 def _drop_left_tail(mp):     # Qbar with the right tail only (diagonal and off-diagonal)
     orig = ot.idg_window_matrix
 
-    def one_tail(L, beta, dps=None):
-        R = orig(L, beta, dps)
+    def one_tail(L, max_shift, dps=None):
+        R = orig(L, max_shift, dps)
         k = np.arange(L)
         x, w = _gl(-400.0, 0.0, step=1.0)
         sk = np.sinc(x[:, None] - k[None, :])
         left = (sk * w[:, None]).T @ sk
-        h = ot.shift_half_range(L, beta)
-        return R - left * np.sinc(np.subtract.outer(k, k) * 2 * h / L)
+        return R - left * np.sinc(np.subtract.outer(k, k) * 2 * max_shift / L)
     mp.setattr(ot, "idg_window_matrix", one_tail)
 
 
