@@ -283,6 +283,39 @@ int idg_grid_to_image(const idg_cf32 *grid_d, int32_t grid_size, const float *co
 int idg_image_to_grid(const idg_cf32 *image_d, int32_t grid_size, const float *corr_l_d, const float *corr_m_d,
                       idg_cf32 *grid_d, void *stream);
 
+/*
+ * The optimal window of image domain gridding (§4.3 and Appendix A): the 1-D
+ * taper a[0..L-1] (the subgrid taper is c[j][i] = a_j a_i, §4.2) minimising the
+ * side-lobe energy of the effective window averaged over the sample shifts
+ * |s| <= max_shift (uv pixels from the subgrid centre).  It is the eigenvector
+ * of the smallest eigenvalue eps^2 of the L x L matrix Rbar = Qbar o Sbar.
+ * Table 1 of the paper uses max_shift = (L - beta + 1)/2 for kernel width beta.
+ * The plans of idg_plan with kernel_size beta keep every sample within
+ * (L - 1 - beta)/2 of its subgrid centre; design their taper for
+ * max_shift = (L - beta)/2, half a pixel more: the window's error rises
+ * steeply at the edge of its design range, and samples on the plans' bound
+ * would sit there.  Host code, float64; nothing touches the GPU.
+ *   L          subgrid size, 4 .. 256
+ *   max_shift  0 < max_shift <= L/2
+ *   taper_out  host double [L], written; scaled so that taper_out[L/2] = 1
+ *   eps_out    host double, written: eps, the rms side-lobe level
+ * Errors: IDG_EINVAL (arguments), IDG_ERANGE (eps^2 below 1e-13 of the largest
+ * eigenvalue, beyond float64 resolution; the outputs are still written).
+ */
+int idg_taper_optimal(int32_t L, double max_shift, double *taper_out, double *eps_out);
+
+/*
+ * The correction the master-grid image steps divide by for a subgrid taper
+ * a[0..L-1] (Algorithms 1 and 2, the inverse rms taper): the effective
+ * window's rms over the sample shifts |s| <= max_shift at each image pixel,
+ *   corr_out[X] = L sqrt(sum_{k,l} a_k a_l sinc(x - k) sinc(x - l) sinc(2 max_shift (k - l) / L)),
+ *   x = L X / N (image pixel X, at l = (X - N/2) S / N, in subgrid index units).
+ * Pass it as both corr_l and corr_m, with the max_shift of the plan.  Host code.
+ *   taper      host double [L];  corr_out  host float [N], written;  2 <= N <= 2^20
+ * Errors: IDG_EINVAL.
+ */
+int idg_taper_correction(int32_t L, double max_shift, const double *taper, int32_t N, float *corr_out);
+
 /* Stage timing (the library's own tracing).  While enabled, idg_grid and
  * idg_degrid record a pair of HIP events on their stream around every kernel
  * they queue.  idg_profile_read waits for the recorded events and returns the

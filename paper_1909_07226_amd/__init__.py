@@ -19,6 +19,9 @@ from ._lib import (  # noqa: F401
     grid_subgrids,
     grid_to_image,
     image_to_grid,
+    optimal_taper,
+    taper_shift_for_plan,
+    taper_correction,
     lib,
     profile,
     profile_read,

@@ -22,7 +22,8 @@ SUBGRID_FIELDS = ("bl", "t0", "nt", "c0", "nc", "x0", "y0", "slot", "s1", "s2", 
 EXPORTED = ("idg_plan", "idg_plan_stats", "idg_plan_export", "idg_plan_destroy", "idg_grid", "idg_degrid",
             "idg_grid_subgrids", "idg_subgrid_fft", "idg_add_subgrids", "idg_split_subgrids", "idg_sync",
             "idg_last_error", "idg_version", "idg_profile", "idg_profile_read", "idg_plan_set_tuning",
-            "idg_plan_get_tuning", "idg_grid_to_image", "idg_image_to_grid")
+            "idg_plan_get_tuning", "idg_grid_to_image", "idg_image_to_grid", "idg_taper_optimal",
+            "idg_taper_correction")
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 DEGRID_STANDARD, DEGRID_WIDE = 0, 1
 STAGES = ("gridder", "adder", "degridder", "zero")
@@ -86,6 +87,8 @@ def lib():
         L.idg_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.idg_grid_to_image.argtypes = [vp, i32, vp, vp, vp, vp]
         L.idg_image_to_grid.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.idg_taper_optimal.argtypes = [i32, ctypes.c_double, vp, vp]
+        L.idg_taper_correction.argtypes = [i32, ctypes.c_double, vp, i32, vp]
         for name in EXPORTED:
             if name not in ("idg_plan_destroy", "idg_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -319,6 +322,31 @@ def image_to_grid(image_d, corr_l_d, corr_m_d, grid_d, stream=None):
     """idg_image_to_grid: grid_d [4, N, N] = the adjoint transform of image_d / (corr_m[y] corr_l[x])."""
     src, N, cl, cm, dst = _image_args(image_d, grid_d, corr_l_d, corr_m_d)
     check(lib().idg_image_to_grid(src, N, cl, cm, dst, _stream_ptr(stream)))
+
+
+def taper_shift_for_plan(L, kernel_size):
+    """max_shift to design a taper for the plans of idg_plan: (L - kernel_size)/2 uv pixels, half a
+    pixel beyond the largest sample shift those plans produce, (L - 1 - kernel_size)/2."""
+    return (int(L) - float(kernel_size)) / 2
+
+
+def optimal_taper(L, max_shift):
+    """idg_taper_optimal: (taper [L] float64 with taper[L/2] = 1, eps).  Raises IDGError (IDG_ERANGE)
+    when eps^2 is beyond float64 resolution."""
+    import numpy as np
+    a = np.zeros(int(L), np.float64)
+    eps = ctypes.c_double(0.0)
+    check(lib().idg_taper_optimal(int(L), float(max_shift), a.ctypes.data, ctypes.addressof(eps)))
+    return a, eps.value
+
+
+def taper_correction(taper, max_shift, N):
+    """idg_taper_correction: corr [N] float32 (host) for the 1-D subgrid taper (float64 [L])."""
+    import numpy as np
+    a = np.ascontiguousarray(taper, np.float64)
+    out = np.zeros(int(N), np.float32)
+    check(lib().idg_taper_correction(int(a.size), float(max_shift), a.ctypes.data, int(N), out.ctypes.data))
+    return out
 
 
 def sync(stream=None):

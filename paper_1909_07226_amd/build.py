@@ -50,9 +50,10 @@ def build(verbose=False):
         obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
         _run([hipcc, "-x", lang, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
-    obj = os.path.join(BUILD, "plan_cpp.o")
-    _run([os.environ.get("CXX", "g++"), *CXX_FLAGS, "-c", os.path.join(CSRC, "plan.cpp"), "-o", obj], verbose)
-    objs.append(obj)
+    for src in ("plan.cpp", "taper.cpp"):
+        obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
+        _run([os.environ.get("CXX", "g++"), *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)

@@ -15,6 +15,7 @@
 #include "idg.h"
 #include "internal.h"
 #include "plan.h"
+#include "taper.h"
 
 namespace {
 
@@ -721,6 +722,41 @@ int idg_grid_to_image(const idg_cf32 *grid_d, int32_t grid_size, const float *co
 int idg_image_to_grid(const idg_cf32 *image_d, int32_t grid_size, const float *corr_l_d, const float *corr_m_d,
                       idg_cf32 *grid_d, void *stream) {
   return image_transform("idg_image_to_grid", false, image_d, grid_size, corr_l_d, corr_m_d, grid_d, stream);
+}
+
+static int taper_args(const char *fn, int32_t L, double max_shift) {
+  if (L < 4 || L > 256) return fail(IDG_EINVAL, "%s: L = %d outside [4, 256]", fn, L);
+  if (!std::isfinite(max_shift) || max_shift <= 0.0 || max_shift > 0.5 * double(L))
+    return fail(IDG_EINVAL, "%s: max_shift = %g outside (0, L/2]", fn, max_shift);
+  return IDG_OK;
+}
+
+int idg_taper_optimal(int32_t L, double max_shift, double *taper_out, double *eps_out) {
+  int rc = taper_args("idg_taper_optimal", L, max_shift);
+  if (rc != IDG_OK) return rc;
+  if (!taper_out || !eps_out) return fail(IDG_EINVAL, "idg_taper_optimal: NULL output");
+  try {
+    rc = idg::optimal_taper(L, max_shift, taper_out, eps_out);
+  } catch (const std::bad_alloc &) {
+    return fail(IDG_ENOMEM, "idg_taper_optimal: host allocation");
+  }
+  if (rc == IDG_ERANGE)
+    return fail(IDG_ERANGE, "idg_taper_optimal: eps^2 = %.3g is below float64 resolution (L = %d, max_shift = %g)",
+                *eps_out * *eps_out, L, max_shift);
+  return rc;
+}
+
+int idg_taper_correction(int32_t L, double max_shift, const double *taper, int32_t N, float *corr_out) {
+  int rc = taper_args("idg_taper_correction", L, max_shift);
+  if (rc != IDG_OK) return rc;
+  if (N < 2 || N > (1 << 20)) return fail(IDG_EINVAL, "idg_taper_correction: N = %d outside [2, 2^20]", N);
+  if (!taper || !corr_out) return fail(IDG_EINVAL, "idg_taper_correction: NULL pointer");
+  try {
+    idg::taper_correction(L, max_shift, taper, N, corr_out);
+  } catch (const std::bad_alloc &) {
+    return fail(IDG_ENOMEM, "idg_taper_correction: host allocation");
+  }
+  return IDG_OK;
 }
 
 int idg_subgrid_fft(idg_cf32 *data_d, int64_t count, int32_t subgrid_size, int32_t direction, void *stream) {
