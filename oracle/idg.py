@@ -23,7 +23,10 @@ the design notes of the repository):
   unnormalised.  Degridding (Algorithm 2, "IFFT") uses its conjugate
   transpose, also unnormalised, so that degridding is the exact adjoint of
   gridding on the planned samples.
-* The w-offset of a subgrid is zero: the w-term is carried by w_k n'_ij.
+* W-offset: subgrid p of W-layer j has w_0p = j * w_step (Algorithms 1 and 2
+  subtract w_0p; without layers w_step = 0 and the whole w-term is carried by
+  w_k n'_ij).  With layers the master grid is one [4, N, N] grid per layer,
+  ``grid[j - wlayer_min]``; the image steps apply exp(+-2 pi i w_0 n') per layer.
 """
 
 import numpy as np
@@ -85,7 +88,7 @@ def grid_subgrid_image(plan, p, uvw, freqs, vis, aterms, taper):
     u, v, w = sample_uvw(uvw, freqs, bl, tc)
     u0, v0 = subgrid_centre(sub, N, L, S)
     l, m, nprime = lmn(L, S)
-    e = phasor_matrix(u - u0, v - v0, w, l, m, nprime, +1.0)            # [K, L*L]
+    e = phasor_matrix(u - u0, v - v0, w - plan.w_offset(p), l, m, nprime, +1.0)   # [K, L*L]
     y = np.asarray(vis[bl, tc[:, 0], tc[:, 1]], dtype=np.complex128)     # [K, 4]
     s = e.T @ y                                                         # [L*L, 4]
     a1 = _jones(aterms, sub[F["slot"]], sub[F["st1"]], L)
@@ -112,15 +115,22 @@ def grid_subgrid(plan, p, uvw, freqs, vis, aterms, taper):
     return forward_subgrid_dft(grid_subgrid_image(plan, p, uvw, freqs, vis, aterms, taper))
 
 
+def layer_grid(plan, g, p):
+    """The [4, N, N] grid of subgrid p's W-layer inside g ([4, N, N], or [layers, 4, N, N] with layers)."""
+    return g[plan.subgrids[p, F["wlayer"]] - plan.wlayer_min] if plan.w_step > 0 else g
+
+
 def grid(plan, uvw, freqs, vis, aterms, taper, subgrid_ids=None, out=None):
-    """Master grid [4, N, N] complex128: the sum of all subgrids added at their corners."""
+    """Master grid complex128, [4, N, N] ([nr_wlayers, 4, N, N] with W-layers): the sum of all
+    subgrids added at their corners."""
     N, L = plan.grid_size, plan.subgrid_size
-    g = np.zeros((4, N, N), np.complex128) if out is None else out
+    shape = (plan.nr_wlayers, 4, N, N) if plan.w_step > 0 else (4, N, N)
+    g = np.zeros(shape, np.complex128) if out is None else out
     ids = range(plan.nr_subgrids) if subgrid_ids is None else subgrid_ids
     for p in ids:
         sub = plan.subgrids[p]
         x0, y0 = sub[F["x0"]], sub[F["y0"]]
-        g[:, y0:y0 + L, x0:x0 + L] += grid_subgrid(plan, p, uvw, freqs, vis, aterms, taper)
+        layer_grid(plan, g, p)[:, y0:y0 + L, x0:x0 + L] += grid_subgrid(plan, p, uvw, freqs, vis, aterms, taper)
     return g
 
 
@@ -129,7 +139,7 @@ def degrid_subgrid(plan, p, uvw, freqs, grid_in, aterms, taper):
     N, L, S = plan.grid_size, plan.subgrid_size, plan.image_size
     sub = plan.subgrids[p]
     x0, y0 = sub[F["x0"]], sub[F["y0"]]
-    vp = np.asarray(grid_in[:, y0:y0 + L, x0:x0 + L], dtype=np.complex128)
+    vp = np.asarray(layer_grid(plan, grid_in, p)[:, y0:y0 + L, x0:x0 + L], dtype=np.complex128)
     img = inverse_subgrid_dft(vp).reshape(4, L * L).T                  # [L*L, 4]
     a1 = _jones(aterms, sub[F["slot"]], sub[F["st1"]], L)
     a2 = _jones(aterms, sub[F["slot"]], sub[F["st2"]], L)
@@ -139,7 +149,7 @@ def degrid_subgrid(plan, p, uvw, freqs, grid_in, aterms, taper):
     u, v, w = sample_uvw(uvw, freqs, sub[F["bl"]], tc)
     u0, v0 = subgrid_centre(sub, N, L, S)
     l, m, nprime = lmn(L, S)
-    e = phasor_matrix(u - u0, v - v0, w, l, m, nprime, -1.0)            # [K, L*L]
+    e = phasor_matrix(u - u0, v - v0, w - plan.w_offset(p), l, m, nprime, -1.0)  # [K, L*L]
     return e @ b
 
 

@@ -82,3 +82,33 @@ def image_to_grid_at(image, us, vs, corr_l, corr_m):
             du, dv = _centred_row(N, u, -1) * cl, _centred_row(N, v, -1) * cm
             out[p, i] = dv @ (ip @ du)
     return out
+
+
+def nprime_image(N, S):
+    """n'(l_x, m_y) = sqrt(1 - l^2 - m^2) - 1 at the master-grid image pixels [y, x] (0 under the
+    square root outside the unit circle, where no sky exists)."""
+    l = (np.arange(N) - N // 2) * float(S) / N
+    r2 = l[None, :] ** 2 + l[:, None] ** 2
+    return np.sqrt(np.maximum(0.0, 1.0 - r2)) - 1.0
+
+
+def wstack_to_image(grids, w0s, S, corr_l, corr_m):
+    """Image [4, N, N] from W-layer grids [layers, 4, N, N] with offsets w0s [layers]:
+    sum_j exp(+2 pi i w0_j n'(l, m)) grid_to_image(grids[j]) -- the w-term the layer's subgrids left
+    out (w_k - w0_j) put back in the image domain -- divided by the correction."""
+    g = np.asarray(grids, np.complex128)
+    N = g.shape[-1]
+    n1 = nprime_image(N, S)
+    ones = np.ones(N)
+    img = sum(np.exp(2j * np.pi * float(w0) * n1) * grid_to_image(g[j], ones, ones) for j, w0 in enumerate(w0s))
+    return img / np.outer(np.asarray(corr_m, np.float64), np.asarray(corr_l, np.float64))
+
+
+def image_to_wstack(image, w0s, S, corr_l, corr_m):
+    """W-layer grids [layers, 4, N, N]: the adjoint of wstack_to_image."""
+    im = np.asarray(image, np.complex128)
+    N = im.shape[-1]
+    n1 = nprime_image(N, S)
+    ones = np.ones(N)
+    x = im / np.outer(np.asarray(corr_m, np.float64), np.asarray(corr_l, np.float64))
+    return np.stack([image_to_grid(np.exp(-2j * np.pi * float(w0) * n1) * x, ones, ones) for w0 in w0s])

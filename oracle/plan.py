@@ -17,6 +17,13 @@ Rule (all geometry in float64, no fused multiply-add):
   u_x = (x - N/2)/S); w-support wpix = ceil((|w| * S) * S) pixels.
 * A set of samples fits iff  (max x - min x) + (beta + max wpix) <= L - 1  and
   the same for y.  Flags do not enter the geometry.
+* W-layers (w_step > 0; the offset w_0p of Algorithms 1 and 2): a block's
+  layer is j = floor(w_mid / w_step + 0.5) with w_mid = (w(t0, c_lo) +
+  w(t0, c_hi)) * 0.5 the mid-band w of its first timestep (w is linear in
+  frequency), its offset w_0p = j * w_step, and the w-support of a sample
+  becomes ceil((|w - w_0p| * S) * S).  In the channel-group step a timestep
+  taken alone uses its own layer.  With w_step = 0 every layer is 0 and
+  w_0p = 0.
 * Per baseline, channels are grouped first: start from one group with all
   channels; a group of more than one channel that does not fit at some
   timestep (taking that timestep's samples alone) is split into a lower half
@@ -33,7 +40,7 @@ Rule (all geometry in float64, no fused multiply-add):
 * Subgrids are ordered by baseline, channel group, then time; each subgrid's
   samples are its unflagged (t, c) in t-major, c-minor order.
 
-Output: ``Plan.subgrids`` int64 [P, 12] with the columns of ``FIELDS`` and
+Output: ``Plan.subgrids`` int64 [P, 13] with the columns of ``FIELDS`` and
 ``Plan.samples`` int64 [K, 2] of absolute (t, c).
 """
 
@@ -43,7 +50,7 @@ import numpy as np
 
 C0 = 299792458.0
 
-FIELDS = ("bl", "t0", "nt", "c0", "nc", "x0", "y0", "slot", "st1", "st2", "nvis", "vis_offset")
+FIELDS = ("bl", "t0", "nt", "c0", "nc", "x0", "y0", "slot", "st1", "st2", "nvis", "vis_offset", "wlayer")
 F = {name: i for i, name in enumerate(FIELDS)}
 
 
@@ -58,15 +65,28 @@ class Plan:
     nr_baselines: int
     nr_timesteps: int
     nr_channels: int
-    subgrids: np.ndarray      # int64 [P, 12]
+    subgrids: np.ndarray      # int64 [P, 13]
     samples: np.ndarray       # int64 [K, 2]  (t, c)
     nr_gridded: int
     nr_dropped: int
     nr_flagged: int
+    w_step: float = 0.0
 
     @property
     def nr_subgrids(self):
         return self.subgrids.shape[0]
+
+    @property
+    def wlayer_min(self):
+        return int(self.subgrids[:, F["wlayer"]].min()) if self.nr_subgrids else 0
+
+    @property
+    def nr_wlayers(self):
+        return int(self.subgrids[:, F["wlayer"]].max()) - self.wlayer_min + 1 if self.nr_subgrids else 1
+
+    def w_offset(self, p):
+        """w_0p of subgrid p in wavelengths."""
+        return float(self.subgrids[p, F["wlayer"]]) * self.w_step
 
     def subgrid_samples(self, p):
         off, n = self.subgrids[p, F["vis_offset"]], self.subgrids[p, F["nvis"]]
@@ -79,7 +99,7 @@ def _fits(span_x, span_y, wmax, beta, L):
 
 
 def make_plan(grid_size, image_size, subgrid_size, kernel_size, max_timesteps, aterm_timesteps,
-              baselines, uvw, freqs, flags=None):
+              baselines, uvw, freqs, flags=None, w_step=0.0):
     N, S, L, beta = int(grid_size), float(image_size), int(subgrid_size), int(kernel_size)
     tmax, aslot = int(max_timesteps), int(aterm_timesteps)
     uvw = np.asarray(uvw, dtype=np.float64)
@@ -93,15 +113,26 @@ def make_plan(grid_size, image_size, subgrid_size, kernel_size, max_timesteps, a
     n_grid = n_drop = 0
     n_flag = 0 if flags is None else int(np.count_nonzero(flags))
 
+    w_step = float(w_step)
     for b in range(nbl):
         x = uvw[b, :, 0][:, None] * s[None, :] * S + half_n          # [nt, nch]
         y = uvw[b, :, 1][:, None] * s[None, :] * S + half_n
-        wpix = np.ceil(np.abs(uvw[b, :, 2][:, None] * s[None, :]) * S * S)
+        w = uvw[b, :, 2][:, None] * s[None, :]                       # wavelengths
         unflagged = np.ones((nt, nch), bool) if flags is None else (np.asarray(flags[b]) == 0)
+
+        def layers(lo, hi):
+            """W-layer of each timestep taken as a block start, for channels [lo, hi)."""
+            if w_step <= 0.0:
+                return np.zeros(nt)
+            return np.floor((w[:, lo] + w[:, hi - 1]) * 0.5 / w_step + 0.5)
+
+        def wsupport(lo, hi, w0):
+            """[nt] max over channels of ceil(|w - w0| S^2), w0 per timestep."""
+            return np.ceil(np.abs(w[:, lo:hi] - w0[:, None]) * S * S).max(1)
 
         def group_stats(lo, hi):
             return (x[:, lo:hi].min(1), x[:, lo:hi].max(1), y[:, lo:hi].min(1), y[:, lo:hi].max(1),
-                    wpix[:, lo:hi].max(1))
+                    wsupport(lo, hi, layers(lo, hi) * w_step))
 
         groups = []
 
@@ -123,6 +154,7 @@ def make_plan(grid_size, image_size, subgrid_size, kernel_size, max_timesteps, a
         for lo, hi in groups:
             mnx, mxx, mny, mxy, wm = group_stats(lo, hi)
             alone = _fits(mxx - mnx, mxy - mny, wm, beta, L)
+            lay = layers(lo, hi)
             t = 0
             while t < nt:
                 if not alone[t]:
@@ -134,7 +166,8 @@ def make_plan(grid_size, image_size, subgrid_size, kernel_size, max_timesteps, a
                 cmxx = np.maximum.accumulate(mxx[t:t_lim])
                 cmny = np.minimum.accumulate(mny[t:t_lim])
                 cmxy = np.maximum.accumulate(mxy[t:t_lim])
-                cwm = np.maximum.accumulate(wm[t:t_lim])
+                w0 = np.full(nt, lay[t] * w_step)                   # the block's offset for every timestep
+                cwm = np.maximum.accumulate(wsupport(lo, hi, w0)[t:t_lim])
                 ok = _fits(cmxx - cmnx, cmxy - cmny, cwm, beta, L)
                 bad = np.flatnonzero(~ok)
                 n_ok = ok.size if bad.size == 0 else int(bad[0])
@@ -154,15 +187,15 @@ def make_plan(grid_size, image_size, subgrid_size, kernel_size, max_timesteps, a
                 tt, cc = np.nonzero(sel)
                 samples.append(np.stack([tt + t0, cc + lo], axis=1))
                 rows.append([b, t0, t1 - t0, lo, hi - lo, int(x0), int(y0), t0 // aslot,
-                             int(baselines[b][0]), int(baselines[b][1]), kp, n_grid])
+                             int(baselines[b][0]), int(baselines[b][1]), kp, n_grid, int(lay[t0])])
                 n_grid += kp
 
     sub = np.array(rows, dtype=np.int64).reshape(-1, len(FIELDS))
     smp = np.concatenate(samples).astype(np.int64, copy=False) if samples else np.zeros((0, 2), np.int64)
-    return Plan(N, S, L, beta, tmax, aslot, nbl, nt, nch, sub, smp, n_grid, n_drop, n_flag)
+    return Plan(N, S, L, beta, tmax, aslot, nbl, nt, nch, sub, smp, n_grid, n_drop, n_flag, w_step)
 
 
-def plan_workload(wl):
+def plan_workload(wl, w_step=0.0):
     """Plan a ``synth.Workload`` (convenience wrapper)."""
     return make_plan(wl.grid_size, wl.image_size, wl.subgrid_size, wl.kernel_size, wl.max_timesteps,
-                     wl.aterm_timesteps, wl.baselines, wl.uvw, wl.freqs, wl.flags)
+                     wl.aterm_timesteps, wl.baselines, wl.uvw, wl.freqs, wl.flags, w_step)
