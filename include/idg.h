@@ -90,6 +90,8 @@ typedef struct {
                               A budget that holds every subgrid of the plan grids it in one launch.
                               The scratch comes from the device's default stream-ordered memory pool,
                               whose release threshold the library raises so freed scratch is reused. */
+  double w_step;           /* W-layer spacing in wavelengths (>= 0; 0 = no layers: every subgrid has
+                              w offset 0 and the grid is one [4][N][N] array) */
 } idg_params;
 
 /*
@@ -109,6 +111,16 @@ typedef struct {
  * are samples that do not fit alone.  Subgrids are ordered by baseline,
  * channel group, time.
  *
+ * W-layers (w_step > 0; the per-subgrid w offset w_0p of Algorithms 1 and 2):
+ * a block's layer is j = floor(w_mid / w_step + 0.5), w_mid = (w(t0, c_lo) +
+ * w(t0, c_hi)) * 0.5 being the mid-band w of its first timestep; its offset is
+ * w_0p = j * w_step and the w-support of a sample becomes ceil((|w - w_0p| * S)
+ * * S).  (In the channel-group step a timestep taken alone uses its own
+ * layer.)  The grids of idg_grid and idg_degrid then hold one [4][N][N] grid
+ * per layer j = wlayer_min .. wlayer_min + nr_wlayers - 1 (idg_plan_wlayers),
+ * consecutively; each layer's grid lacks the w-term w_0p n', which the image
+ * steps (idg_wstack_to_image, idg_image_to_wstack) put back.
+ *
  *   params     sizes and options (copied)
  *   baselines  host int32 [nr_baselines][2], stations in [0, nr_stations), s1 != s2
  *   uvw        host float64 [nr_baselines][nr_timesteps][3], finite
@@ -127,8 +139,13 @@ int idg_plan(const idg_params *params, const int32_t *baselines, const double *u
 int idg_plan_stats(idg_plan_t plan, int64_t *nr_subgrids, int64_t *nr_gridded, int64_t *nr_dropped,
                    int64_t *nr_flagged);
 
+/* W-layers of the plan (either pointer may be NULL): the grid passed to
+ * idg_grid / idg_degrid is [nr_wlayers][4][N][N], layer index j - wlayer_min.
+ * Without layers wlayer_min = 0 and nr_wlayers = 1. */
+int idg_plan_wlayers(idg_plan_t plan, int32_t *wlayer_min, int32_t *nr_wlayers);
+
 /* Copy the plan to host arrays (either may be NULL):
- *   subgrids  int64 [nr_subgrids][12]: bl, t0, nt, c0, nc, x0, y0, slot, s1, s2, nvis, vis_offset
+ *   subgrids  int64 [nr_subgrids][13]: bl, t0, nt, c0, nc, x0, y0, slot, s1, s2, nvis, vis_offset, wlayer
  *   samples   int32 [nr_gridded][2]: (timestep, channel) of each planned sample,
  *             grouped by subgrid (rows vis_offset .. vis_offset + nvis - 1), t-major. */
 int idg_plan_export(idg_plan_t plan, int64_t *subgrids, int32_t *samples);
@@ -196,7 +213,9 @@ void idg_plan_destroy(idg_plan_t plan);
  *   uvw_d    float64 [nr_baselines][nr_timesteps][3]     freqs_d  float64 [nr_channels]
  *   vis_d    complex64 [nr_baselines][nr_timesteps][nr_channels][4]
  *   aterms_d complex64 [nr_slots][nr_stations][L][L][4]  taper_d  float32 [L][L]
- *   grid_d   complex64 [4][N][N], read and written
+ *   grid_d   complex64 [nr_wlayers][4][N][N] ([4][N][N] without W-layers), read and
+ *            written; a subgrid of layer j is added to grid j - wlayer_min
+ * With W-layers the phase of sample k in subgrid p uses w_k - w_0p.
  * Errors: IDG_EINVAL (NULL pointer), IDG_ENOMEM, IDG_EHIP.
  */
 int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
@@ -206,7 +225,7 @@ int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const 
  * Image-domain degridding (Algorithm 2 after its first two lines): for every
  * subgrid, split it out of grid_d, apply the unnormalised inverse centred DFT,
  * apply c * A_s1 I A_s2^H per pixel, and for every sample compute
- * sum_pix B exp(-2 pi i (du_k l + dv_k m + w_k n')).  vis_d is OVERWRITTEN:
+ * sum_pix B exp(-2 pi i (du_k l + dv_k m + (w_k - w_0p) n')).  vis_d is OVERWRITTEN:
  * planned samples get their prediction, flagged and dropped samples get 0.
  * Arguments as idg_grid, grid_d read only, vis_d written.
  * Errors: IDG_EINVAL, IDG_ENOMEM, IDG_EHIP.
@@ -282,6 +301,31 @@ int idg_grid_to_image(const idg_cf32 *grid_d, int32_t grid_size, const float *co
  */
 int idg_image_to_grid(const idg_cf32 *image_d, int32_t grid_size, const float *corr_l_d, const float *corr_m_d,
                       idg_cf32 *grid_d, void *stream);
+
+/*
+ * W-stacked image steps (the w offsets w_0p of Algorithms 1 and 2): each layer's
+ * grid lacks the w-term w_0 n' of its subgrids, which is put back per layer in
+ * the image domain,
+ *   image_d = sum_j exp(+2 pi i w0s[j] n'(l_x, m_y)) T(grids_d[j]) / (corr_m_d[y] corr_l_d[x]),
+ * T being the transform of idg_grid_to_image and n' = sqrt(1 - l^2 - m^2) - 1
+ * at l_x = (x - N/2) S / N, m_y = (y - N/2) S / N (0 under the root outside the
+ * unit circle).  idg_image_to_wstack is its adjoint (every grid OVERWRITTEN):
+ *   grids_d[j] = T^H(image_d exp(-2 pi i w0s[j] n') / (corr_m_d[y] corr_l_d[x])).
+ *   grids_d     device complex64 [nr_wlayers][4][N][N]; for a plan, the layer
+ *               grids of idg_grid / idg_degrid, w0s[j] = (wlayer_min + j) w_step
+ *   w0s         host float64 [nr_wlayers], finite (read during the call)
+ *   image_d     device complex64 [4][N][N], must not overlap grids_d
+ *   image_size  S in (0, 1.4];  corrections as idg_grid_to_image
+ * N = grid_size a power of two in [64, 16384], 1 <= nr_wlayers <= 65536.  One
+ * layer at a time through 4 N^2 x 8 bytes of stream-ordered scratch.
+ * Errors: IDG_EINVAL, IDG_ENOMEM, IDG_EHIP.
+ */
+int idg_wstack_to_image(const idg_cf32 *grids_d, int32_t nr_wlayers, const double *w0s, int32_t grid_size,
+                        double image_size, const float *corr_l_d, const float *corr_m_d, idg_cf32 *image_d,
+                        void *stream);
+int idg_image_to_wstack(const idg_cf32 *image_d, int32_t grid_size, double image_size, const float *corr_l_d,
+                        const float *corr_m_d, int32_t nr_wlayers, const double *w0s, idg_cf32 *grids_d,
+                        void *stream);
 
 /*
  * The optimal window of image domain gridding (§4.3 and Appendix A): the 1-D

@@ -21,6 +21,8 @@ from ._lib import (  # noqa: F401
     image_to_grid,
     optimal_taper,
     taper_shift_for_plan,
+    wstack_to_image,
+    image_to_wstack,
     taper_correction,
     lib,
     profile,

@@ -17,13 +17,13 @@ IDG_OK, IDG_EINVAL, IDG_ENOMEM, IDG_EHIP, IDG_ERANGE, IDG_ESTATE = 0, -1, -2, -3
 IDG_STRICT = 1 << 0
 IDG_PHASE_FP32 = 1 << 1
 
-SUBGRID_FIELDS = ("bl", "t0", "nt", "c0", "nc", "x0", "y0", "slot", "s1", "s2", "nvis", "vis_offset")
+SUBGRID_FIELDS = ("bl", "t0", "nt", "c0", "nc", "x0", "y0", "slot", "s1", "s2", "nvis", "vis_offset", "wlayer")
 
 EXPORTED = ("idg_plan", "idg_plan_stats", "idg_plan_export", "idg_plan_destroy", "idg_grid", "idg_degrid",
             "idg_grid_subgrids", "idg_subgrid_fft", "idg_add_subgrids", "idg_split_subgrids", "idg_sync",
             "idg_last_error", "idg_version", "idg_profile", "idg_profile_read", "idg_plan_set_tuning",
             "idg_plan_get_tuning", "idg_grid_to_image", "idg_image_to_grid", "idg_taper_optimal",
-            "idg_taper_correction")
+            "idg_taper_correction", "idg_plan_wlayers", "idg_wstack_to_image", "idg_image_to_wstack")
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 DEGRID_STANDARD, DEGRID_WIDE = 0, 1
 STAGES = ("gridder", "adder", "degridder", "zero")
@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
                 ("max_timesteps", ctypes.c_int32), ("aterm_timesteps", ctypes.c_int32),
                 ("nr_stations", ctypes.c_int32), ("nr_baselines", ctypes.c_int32), ("nr_timesteps", ctypes.c_int32),
                 ("nr_channels", ctypes.c_int32), ("flags", ctypes.c_uint32), ("image_size", ctypes.c_double),
-                ("scratch_bytes", ctypes.c_int64)]
+                ("scratch_bytes", ctypes.c_int64), ("w_step", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -89,6 +89,9 @@ def lib():
         L.idg_image_to_grid.argtypes = [vp, i32, vp, vp, vp, vp]
         L.idg_taper_optimal.argtypes = [i32, ctypes.c_double, vp, vp]
         L.idg_taper_correction.argtypes = [i32, ctypes.c_double, vp, i32, vp]
+        L.idg_plan_wlayers.argtypes = [vp, vp, vp]
+        L.idg_wstack_to_image.argtypes = [vp, i32, vp, i32, ctypes.c_double, vp, vp, vp, vp]
+        L.idg_image_to_wstack.argtypes = [vp, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp]
         for name in EXPORTED:
             if name not in ("idg_plan_destroy", "idg_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -138,14 +141,15 @@ class Plan:
     """A subgrid plan (idg_plan).  Host arrays in, opaque handle kept."""
 
     def __init__(self, grid_size, image_size, subgrid_size, kernel_size, max_timesteps, aterm_timesteps,
-                 nr_stations, baselines, uvw, freqs, flags=None, strict=False, phase_fp32=False, scratch_bytes=0):
+                 nr_stations, baselines, uvw, freqs, flags=None, strict=False, phase_fp32=False, scratch_bytes=0,
+                 w_step=0.0):
         uvw = np.asarray(uvw)
         nbl, nt = uvw.shape[0], uvw.shape[1]
         nch = int(np.asarray(freqs).size)
         self.params = Params(int(grid_size), int(subgrid_size), int(kernel_size), int(max_timesteps),
                              int(aterm_timesteps), int(nr_stations), nbl, nt, nch,
                              (IDG_STRICT if strict else 0) | (IDG_PHASE_FP32 if phase_fp32 else 0),
-                             float(image_size), int(scratch_bytes))
+                             float(image_size), int(scratch_bytes), float(w_step))
         self._keep = []
         bl, blp = _host_ptr(baselines, np.int32, (nbl, 2), "baselines")
         uv, uvp = _host_ptr(uvw, np.float64, (nbl, nt, 3), "uvw")
@@ -187,6 +191,17 @@ class Plan:
     def nr_subgrids(self):
         return self.stats()["nr_subgrids"]
 
+    def wlayers(self):
+        """(wlayer_min, nr_wlayers): the grid is [nr_wlayers][4][N][N], layer j at index j - wlayer_min."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().idg_plan_wlayers(self._handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def w_offsets(self):
+        """w offset (wavelengths) of each layer grid, in grid order."""
+        lo, n = self.wlayers()
+        return [(lo + j) * self.params.w_step for j in range(n)]
+
     def set_tuning(self, form=None, blocks_per_cu=None, adder_chunk=None, grid_form=None, degrid_form=None,
                    grid_blocks_per_cu=None, degrid_blocks_per_cu=None, degrid_shape=None):
         """Scheduling knobs (idg_plan_set_tuning).  ``form`` / ``blocks_per_cu`` set both directions;
@@ -213,9 +228,9 @@ class Plan:
                     adder_chunk=t.adder_chunk, degrid_shape=_SHAPE_NAMES.get(t.degrid_shape, t.degrid_shape))
 
     def export(self):
-        """(subgrids int64 [P, 12] with SUBGRID_FIELDS columns, samples int32 [K, 2] of (t, c))."""
+        """(subgrids int64 [P, 13] with SUBGRID_FIELDS columns, samples int32 [K, 2] of (t, c))."""
         st = self.stats()
-        sub = np.zeros((st["nr_subgrids"], 12), np.int64)
+        sub = np.zeros((st["nr_subgrids"], len(SUBGRID_FIELDS)), np.int64)
         smp = np.zeros((st["nr_gridded"], 2), np.int32)
         check(lib().idg_plan_export(self._handle, sub.ctypes.data_as(ctypes.c_void_p),
                                     smp.ctypes.data_as(ctypes.c_void_p)))
@@ -228,7 +243,7 @@ class Plan:
         ns = -(-p.nr_timesteps // p.aterm_timesteps) if nr_slots is None else nr_slots
         return dict(uvw=(p.nr_baselines, p.nr_timesteps, 3), freqs=(p.nr_channels,),
                     vis=(p.nr_baselines, p.nr_timesteps, p.nr_channels, 4), aterms=(ns, p.nr_stations, L, L, 4),
-                    taper=(L, L), grid=(4, N, N))
+                    taper=(L, L), grid=(4, N, N) if p.w_step == 0 else (self.wlayers()[1], 4, N, N))
 
 
 def _common(plan, uvw_d, freqs_d, aterms_d, taper_d):
@@ -328,6 +343,34 @@ def taper_shift_for_plan(L, kernel_size):
     """max_shift to design a taper for the plans of idg_plan: (L - kernel_size)/2 uv pixels, half a
     pixel beyond the largest sample shift those plans produce, (L - 1 - kernel_size)/2."""
     return (int(L) - float(kernel_size)) / 2
+
+
+def _wstack_args(image_d, grids_d, w0s, corr_l_d, corr_m_d):
+    import torch
+    if grids_d.dim() != 4 or grids_d.shape[1] != 4 or grids_d.shape[2] != grids_d.shape[3]:
+        raise ValueError("grids: expected [nr_wlayers, 4, N, N] complex64")
+    nl, N = int(grids_d.shape[0]), int(grids_d.shape[-1])
+    w0 = np.ascontiguousarray(w0s, np.float64)
+    if w0.shape != (nl,):
+        raise ValueError(f"w0s: expected {nl} offsets, got shape {w0.shape}")
+    if (corr_l_d is None) != (corr_m_d is None):
+        raise ValueError("give both corrections or neither")
+    cl = None if corr_l_d is None else _dev_ptr(corr_l_d, torch.float32, (N,), "corr_l")
+    cm = None if corr_m_d is None else _dev_ptr(corr_m_d, torch.float32, (N,), "corr_m")
+    return (_dev_ptr(image_d, torch.complex64, (4, N, N), "image"),
+            _dev_ptr(grids_d, torch.complex64, (nl, 4, N, N), "grids"), nl, N, w0, cl, cm)
+
+
+def wstack_to_image(grids_d, w0s, image_size, corr_l_d, corr_m_d, image_d, stream=None):
+    """idg_wstack_to_image: image_d = sum_j exp(+2 pi i w0s[j] n') T(grids_d[j]) / correction."""
+    img, g, nl, N, w0, cl, cm = _wstack_args(image_d, grids_d, w0s, corr_l_d, corr_m_d)
+    check(lib().idg_wstack_to_image(g, nl, w0.ctypes.data, N, float(image_size), cl, cm, img, _stream_ptr(stream)))
+
+
+def image_to_wstack(image_d, image_size, corr_l_d, corr_m_d, w0s, grids_d, stream=None):
+    """idg_image_to_wstack: grids_d[j] = T^H(image_d exp(-2 pi i w0s[j] n') / correction)."""
+    img, g, nl, N, w0, cl, cm = _wstack_args(image_d, grids_d, w0s, corr_l_d, corr_m_d)
+    check(lib().idg_image_to_wstack(img, N, float(image_size), cl, cm, nl, w0.ctypes.data, g, _stream_ptr(stream)))
 
 
 def optimal_taper(L, max_shift):

@@ -82,15 +82,17 @@ struct TileLists {
 
 // Tile ownership for the adder: for every grid tile, the local indices of the
 // subgrids that overlap it, ascending; tiles with more work first.
+// Tile ids run over the W-layers: (layer - wlayer_min) * ntx^2 + ty * ntx + tx.
 void build_tile_lists(const std::vector<idg::SubgridRec> &subs, int64_t first, int64_t count, int N, int L,
-                      TileLists &out) {
+                      int wlayer_min, int nr_wlayers, TileLists &out) {
   const int T = idg::kAdderTile;
   const int ntx = (N + T - 1) / T;
-  const int64_t ntile = int64_t(ntx) * ntx;
+  const int64_t ntile = int64_t(ntx) * ntx * nr_wlayers;
   std::vector<int32_t> cnt(size_t(ntile) + 1, 0);
   auto each_tile = [&](const idg::SubgridRec &r, auto &&fn) {
+    const int64_t base = int64_t(r.wlayer - wlayer_min) * ntx * ntx;
     for (int ty = r.y0 / T; ty <= (r.y0 + L - 1) / T; ++ty)
-      for (int tx = r.x0 / T; tx <= (r.x0 + L - 1) / T; ++tx) fn(int64_t(ty) * ntx + tx);
+      for (int tx = r.x0 / T; tx <= (r.x0 + L - 1) / T; ++tx) fn(base + int64_t(ty) * ntx + tx);
   };
   for (int64_t s = 0; s < count; ++s) each_tile(subs[size_t(first + s)], [&](int64_t t) { cnt[size_t(t)]++; });
   std::vector<int64_t> off(size_t(ntile) + 1, 0);
@@ -266,6 +268,8 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
     d.a1 = r.slot * p.nr_stations + r.s1;
     d.a2 = r.slot * p.nr_stations + r.s2;
     d.vis_offset = r.vis_offset;
+    d.w0 = double(r.wlayer) * p.w_step;
+    d.layer = r.wlayer - h.wlayer_min;
     d.pad = 0;
   }
   std::vector<float4> lmn;
@@ -306,7 +310,7 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
     b.order_off = int64_t(grid_order.size());
     grid_order.insert(grid_order.end(), ord.begin(), ord.end());
     TileLists tl;
-    build_tile_lists(h.subgrids, b.first, b.count, p.grid_size, L, tl);
+    build_tile_lists(h.subgrids, b.first, b.count, p.grid_size, L, h.wlayer_min, h.nr_wlayers, tl);
     AdderPlan ap;
     build_adder_plan(tl, chunk, int64_t(all_contrib.size()), ap);
     all_contrib.insert(all_contrib.end(), tl.contrib.begin(), tl.contrib.end());
@@ -380,6 +384,7 @@ int validate_params(const idg_params *p) {
   if (!(p->image_size > 0.0) || !(p->image_size <= 1.4))
     return fail(IDG_EINVAL, "image_size must be in (0, 1.4] (direction cosines)");
   if (p->scratch_bytes < 0) return fail(IDG_EINVAL, "scratch_bytes must be >= 0");
+  if (!std::isfinite(p->w_step) || p->w_step < 0.0) return fail(IDG_EINVAL, "w_step must be finite and >= 0");
   if (p->flags & ~uint32_t(IDG_STRICT | IDG_PHASE_FP32)) return fail(IDG_EINVAL, "unknown flags 0x%x", p->flags);
   const int64_t total = int64_t(p->nr_baselines) * p->nr_timesteps * p->nr_channels;
   if (total > (int64_t(1) << 40)) return fail(IDG_EINVAL, "too many samples");
@@ -390,7 +395,7 @@ int validate_params(const idg_params *p) {
 
 extern "C" {
 
-int idg_version(void) { return 10100; }
+int idg_version(void) { return 10200; }
 
 const char *idg_last_error(void) { return g_last_error.c_str(); }
 
@@ -415,6 +420,13 @@ int idg_plan(const idg_params *params, const int32_t *baselines, const double *u
   for (int c = 0; c < p.nr_channels; ++c)
     if (!std::isfinite(freqs[c]) || !(freqs[c] > 0.0))
       return fail(IDG_EINVAL, "idg_plan: freqs[%d] must be finite and > 0", c);
+  if (p.w_step > 0.0 && nbt > 0 && p.nr_channels > 0) {  // layer indices stay far inside int32
+    double wmax = 0.0, fmax = 0.0;
+    for (int64_t i = 0; i < nbt; ++i) wmax = std::max(wmax, std::fabs(uvw[3 * i + 2]));
+    for (int c = 0; c < p.nr_channels; ++c) fmax = std::max(fmax, freqs[c]);
+    if (wmax * (fmax / idg::kSpeedOfLight) / p.w_step > 1e6)
+      return fail(IDG_EINVAL, "idg_plan: w_step %g gives more than 1e6 W-layers", p.w_step);
+  }
   idg_plan_s *plan = new (std::nothrow) idg_plan_s;
   if (!plan) return fail(IDG_ENOMEM, "idg_plan: out of host memory");
   std::string err;
@@ -422,6 +434,11 @@ int idg_plan(const idg_params *params, const int32_t *baselines, const double *u
   if (rc != IDG_OK) {
     delete plan;
     return fail(rc, "%s", err.c_str());
+  }
+  if (int64_t(plan->host.nr_wlayers) * ((p.grid_size + idg::kAdderTile - 1) / idg::kAdderTile) *
+          ((p.grid_size + idg::kAdderTile - 1) / idg::kAdderTile) >= (int64_t(1) << 31)) {
+    delete plan;
+    return fail(IDG_EINVAL, "idg_plan: W-layers x grid tiles exceed 2^31");
   }
   if ((p.flags & IDG_STRICT) && plan->host.nr_dropped > 0) {
     const long long nd = (long long)plan->host.nr_dropped;
@@ -448,9 +465,10 @@ int idg_plan_export(idg_plan_t plan, int64_t *subgrids, int32_t *samples) {
   if (subgrids) {
     for (size_t i = 0; i < h.subgrids.size(); ++i) {
       const auto &r = h.subgrids[i];
-      int64_t *o = subgrids + i * 12;
+      int64_t *o = subgrids + i * 13;
       o[0] = r.bl; o[1] = r.t0; o[2] = r.nt; o[3] = r.c0; o[4] = r.nc; o[5] = r.x0;
       o[6] = r.y0; o[7] = r.slot; o[8] = r.s1; o[9] = r.s2; o[10] = r.nvis; o[11] = r.vis_offset;
+      o[12] = r.wlayer;
     }
   }
   if (samples) {
@@ -461,6 +479,13 @@ int idg_plan_export(idg_plan_t plan, int64_t *subgrids, int32_t *samples) {
         samples[2 * (r.vis_offset + k) + 1] = r.c0 + int32_t(pk & 0xffffu);
       }
   }
+  return IDG_OK;
+}
+
+int idg_plan_wlayers(idg_plan_t plan, int32_t *wlayer_min, int32_t *nr_wlayers) {
+  if (!plan) return fail(IDG_EINVAL, "idg_plan_wlayers: plan is NULL");
+  if (wlayer_min) *wlayer_min = plan->host.wlayer_min;
+  if (nr_wlayers) *nr_wlayers = plan->host.nr_wlayers;
   return IDG_OK;
 }
 
@@ -724,6 +749,75 @@ int idg_image_to_grid(const idg_cf32 *image_d, int32_t grid_size, const float *c
   return image_transform("idg_image_to_grid", false, image_d, grid_size, corr_l_d, corr_m_d, grid_d, stream);
 }
 
+// W-stacked image steps: one layer at a time through a [4][N][N] scratch.
+static int wstack_args(const char *fn, const void *image, const void *grids, int32_t N, double S, int32_t nl,
+                       const double *w0s, const float *cl, const float *cm) {
+  if (!idg::image_size_supported(N)) return fail(IDG_EINVAL, "%s: grid_size %d is not a power of two in [64, 16384]", fn, N);
+  if (!(S > 0.0) || !(S <= 1.4)) return fail(IDG_EINVAL, "%s: image_size must be in (0, 1.4]", fn);
+  if (nl < 1 || nl > 65536) return fail(IDG_EINVAL, "%s: nr_wlayers %d outside [1, 65536]", fn, nl);
+  if (!image || !grids || !w0s) return fail(IDG_EINVAL, "%s: NULL pointer", fn);
+  if ((cl == nullptr) != (cm == nullptr)) return fail(IDG_EINVAL, "%s: give both corrections or neither", fn);
+  for (int j = 0; j < nl; ++j)
+    if (!std::isfinite(w0s[j])) return fail(IDG_EINVAL, "%s: w0s[%d] is not finite", fn, j);
+  const size_t layer = size_t(4) * N * N * sizeof(idg_cf32);
+  const char *a = static_cast<const char *>(image), *b = static_cast<const char *>(grids);
+  if (a < b + layer * size_t(nl) && b < a + layer) return fail(IDG_EINVAL, "%s: image and grids overlap", fn);
+  return IDG_OK;
+}
+
+int idg_wstack_to_image(const idg_cf32 *grids_d, int32_t nr_wlayers, const double *w0s, int32_t grid_size,
+                        double image_size, const float *corr_l_d, const float *corr_m_d, idg_cf32 *image_d,
+                        void *stream) {
+  int rc = wstack_args("idg_wstack_to_image", image_d, grids_d, grid_size, image_size, nr_wlayers, w0s, corr_l_d,
+                       corr_m_d);
+  if (rc != IDG_OK) return rc;
+  const int N = grid_size;
+  const size_t nn = size_t(4) * N * N;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  float2 *scr = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&scr), (nn + size_t(N) / 2) * sizeof(float2), s),
+          "idg_wstack_to_image: scratch");
+  float2 *tw = scr + nn;
+  const float2 *g = reinterpret_cast<const float2 *>(grids_d);
+  float2 *img = reinterpret_cast<float2 *>(image_d);
+  hipError_t e = idg::launch_image_twiddles(tw, N, s);
+  for (int j = 0; j < nr_wlayers && e == hipSuccess; ++j) {
+    e = idg::launch_grid_to_image(g + nn * j, scr, N, nullptr, nullptr, tw, s);
+    if (e == hipSuccess)
+      e = idg::launch_wlayer_phase(scr, img, N, image_size, w0s[j], +1, j > 0, corr_l_d, corr_m_d, s);
+  }
+  const hipError_t ef = hipFreeAsync(scr, s);
+  if (e != hipSuccess) return hip_fail(e, "idg_wstack_to_image: launch");
+  HIP_TRY(ef, "idg_wstack_to_image: scratch release");
+  return IDG_OK;
+}
+
+int idg_image_to_wstack(const idg_cf32 *image_d, int32_t grid_size, double image_size, const float *corr_l_d,
+                        const float *corr_m_d, int32_t nr_wlayers, const double *w0s, idg_cf32 *grids_d,
+                        void *stream) {
+  int rc = wstack_args("idg_image_to_wstack", image_d, grids_d, grid_size, image_size, nr_wlayers, w0s, corr_l_d,
+                       corr_m_d);
+  if (rc != IDG_OK) return rc;
+  const int N = grid_size;
+  const size_t nn = size_t(4) * N * N;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  float2 *scr = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&scr), (nn + size_t(N) / 2) * sizeof(float2), s),
+          "idg_image_to_wstack: scratch");
+  float2 *tw = scr + nn;
+  const float2 *img = reinterpret_cast<const float2 *>(image_d);
+  float2 *g = reinterpret_cast<float2 *>(grids_d);
+  hipError_t e = idg::launch_image_twiddles(tw, N, s);
+  for (int j = 0; j < nr_wlayers && e == hipSuccess; ++j) {
+    e = idg::launch_wlayer_phase(img, scr, N, image_size, w0s[j], -1, false, corr_l_d, corr_m_d, s);
+    if (e == hipSuccess) e = idg::launch_image_to_grid(scr, g + nn * j, N, nullptr, nullptr, tw, s);
+  }
+  const hipError_t ef = hipFreeAsync(scr, s);
+  if (e != hipSuccess) return hip_fail(e, "idg_image_to_wstack: launch");
+  HIP_TRY(ef, "idg_image_to_wstack: scratch release");
+  return IDG_OK;
+}
+
 static int taper_args(const char *fn, int32_t L, double max_shift) {
   if (L < 4 || L > 256) return fail(IDG_EINVAL, "%s: L = %d outside [4, 256]", fn, L);
   if (!std::isfinite(max_shift) || max_shift <= 0.0 || max_shift > 0.5 * double(L))
@@ -791,7 +885,7 @@ int idg_add_subgrids(idg_plan_t plan, const idg_cf32 *subgrids_d, int64_t first,
   TileLists tl;
   AdderPlan ap;
   try {
-    build_tile_lists(h.subgrids, first, count, p.grid_size, p.subgrid_size, tl);
+    build_tile_lists(h.subgrids, first, count, p.grid_size, p.subgrid_size, h.wlayer_min, h.nr_wlayers, tl);
     build_adder_plan(tl, plan->tuning.adder_chunk > 0 ? plan->tuning.adder_chunk : 256, 0, ap);
   } catch (const std::bad_alloc &) {
     return fail(IDG_ENOMEM, "idg_add_subgrids: out of host memory");

@@ -207,6 +207,57 @@ __global__ void __launch_bounds__(fft_threads(N * C))
   }
 }
 
+// W-layers: out[pol][y][x] (= or +=) in[pol][y][x] exp(SIGN 2 pi i w0 n'(l_x, m_y)) [/ (cm[y] cl[x])],
+// n' = sqrt(1 - l^2 - m^2) - 1 (0 under the root outside the unit circle), l_x = (x - N/2) S / N.
+// One thread per pixel: the phasor, from float64, serves the 4 polarisations.
+template <int SIGN, bool ACC>
+__global__ void __launch_bounds__(256) wlayer_phase_kernel(const float2 *in, float2 *out, int N, double S, double w0,
+                                                           const float *__restrict__ cl,
+                                                           const float *__restrict__ cm) {
+  const int64_t NN = int64_t(N) * N;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= NN) return;
+  const int y = int(i / N), x = int(i % N);
+  const double l = double(x - N / 2) * S / double(N), m = double(y - N / 2) * S / double(N);
+  const double n1 = sqrt(fmax(0.0, 1.0 - l * l - m * m)) - 1.0;
+  double ph = w0 * n1;
+  ph -= floor(ph);
+  double sn, cs;
+  sincospi(2.0 * ph, &sn, &cs);
+  float2 e = make_float2(float(cs), float(SIGN > 0 ? sn : -sn));
+  if (cl) {
+    const float f = 1.0f / (cm[y] * cl[x]);
+    e = make_float2(e.x * f, e.y * f);
+  }
+#pragma unroll
+  for (int pol = 0; pol < 4; ++pol) {
+    float2 v = fmul(in[pol * NN + i], e);
+    if (ACC) {
+      const float2 o = out[pol * NN + i];
+      v = make_float2(o.x + v.x, o.y + v.y);
+    }
+    out[pol * NN + i] = v;
+  }
+}
+
+hipError_t launch_wlayer_phase(const float2 *in, float2 *out, int N, double S, double w0, int sign, bool accumulate,
+                               const float *corr_l, const float *corr_m, hipStream_t s) {
+  const int64_t NN = int64_t(N) * N;
+  const dim3 grid(unsigned((NN + 255) / 256)), block(256);
+  if (sign > 0) {
+    if (accumulate)
+      hipLaunchKernelGGL((wlayer_phase_kernel<1, true>), grid, block, 0, s, in, out, N, S, w0, corr_l, corr_m);
+    else
+      hipLaunchKernelGGL((wlayer_phase_kernel<1, false>), grid, block, 0, s, in, out, N, S, w0, corr_l, corr_m);
+  } else {
+    if (accumulate)
+      hipLaunchKernelGGL((wlayer_phase_kernel<-1, true>), grid, block, 0, s, in, out, N, S, w0, corr_l, corr_m);
+    else
+      hipLaunchKernelGGL((wlayer_phase_kernel<-1, false>), grid, block, 0, s, in, out, N, S, w0, corr_l, corr_m);
+  }
+  return hipGetLastError();
+}
+
 bool image_size_supported(int N) { return N >= 64 && N <= 16384 && (N & (N - 1)) == 0; }
 
 // Elements per workgroup: rows, at least kRowElems (whole rows); columns, at

@@ -15,9 +15,11 @@ struct alignas(16) DevSubgrid {
   int32_t x0, y0;
   int32_t a1, a2;      // Jones block index (slot * nr_stations + station) of stations s1, s2
   int64_t vis_offset;  // first packed sample of this subgrid
-  int64_t pad;
+  double w0;           // w offset of the subgrid's W-layer, wavelengths (0 without layers)
+  int32_t layer;       // index of that layer's [4][N][N] grid
+  int32_t pad;
 };
-static_assert(sizeof(DevSubgrid) == 48, "DevSubgrid layout");
+static_assert(sizeof(DevSubgrid) == 64, "DevSubgrid layout");
 
 // Arguments of the gridder / degridder kernels.
 struct KernelArgs {
@@ -96,5 +98,9 @@ hipError_t launch_grid_to_image(const float2 *grid, float2 *image, int N, const 
                                 const float2 *tw, hipStream_t s);
 hipError_t launch_image_to_grid(const float2 *image, float2 *grid, int N, const float *corr_l, const float *corr_m,
                                 const float2 *tw, hipStream_t s);
+
+// out (= or +=) in * exp(sign 2 pi i w0 n'(l, m)) [/ (corr_m[y] corr_l[x])] over [4][N][N]
+hipError_t launch_wlayer_phase(const float2 *in, float2 *out, int N, double S, double w0, int sign, bool accumulate,
+                               const float *corr_l, const float *corr_m, hipStream_t s);
 
 }  // namespace idg

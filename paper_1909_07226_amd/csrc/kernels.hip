@@ -449,7 +449,8 @@ __device__ __forceinline__ void grid_one(const KernelArgs &a, int local, Gridder
   const double v0 = double(d.y0 + L / 2 - a.grid_size / 2) / S;
   float p0[PPT];
 #pragma unroll
-  for (int r = 0; r < PPT; ++r) p0[r] = FP32_PHASE ? float(u0) * pc.l[r] + float(v0) * pc.m[r] : 0.0f;
+  for (int r = 0; r < PPT; ++r)
+    p0[r] = FP32_PHASE ? float(u0) * pc.l[r] + float(v0) * pc.m[r] + float(d.w0) * pc.n[r] : 0.0f;
   const bool recur = !FP32_PHASE && a.chan_recur != 0;
 
   float2 acc[PPT][4];
@@ -487,7 +488,7 @@ __device__ __forceinline__ void grid_one(const KernelArgs &a, int local, Gridder
         const float sf = float(s);
         o = make_float4(float(q[0]) * sf, float(q[1]) * sf, float(q[2]) * sf, __int_as_float(len));
       } else {
-        o = make_float4(float(q[0] * s - u0), float(q[1] * s - v0), float(q[2] * s), __int_as_float(len));
+        o = make_float4(float(q[0] * s - u0), float(q[1] * s - v0), float(q[2] * s - d.w0), __int_as_float(len));
       }
       s_uvw[tid] = o;
       if (len > 1) {
@@ -629,7 +630,7 @@ template <int L, int V, bool FP32_PHASE, bool RECUR>
 __device__ __forceinline__ void degrid_pixels(float2 (&y)[V][4], const float (&du)[V], const float (&dv)[V],
                                               const float (&w)[V], float sx, float sy, float sz,
                                               const KernelArgs &a, const float4 *s_b, const float4 *s_lmn,
-                                              int lo, int hi, float u0f, float v0f) {
+                                              int lo, int hi, float u0f, float v0f, float w0f) {
   constexpr bool LMN_LDS = DegridderSmem<L>::LMN_LDS;
   constexpr int UNROLL = V >= 8 ? 1 : 2;
 #pragma unroll UNROLL
@@ -651,7 +652,7 @@ __device__ __forceinline__ void degrid_pixels(float2 (&y)[V][4], const float (&d
         cmac(y[v][3], b23.z, b23.w, e.x, -e.y);
       }
     } else {
-      const float off = FP32_PHASE ? u0f * q.x + v0f * q.y : 0.0f;
+      const float off = FP32_PHASE ? u0f * q.x + v0f * q.y + w0f * q.z : 0.0f;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         float ph = du[v] * q.x + dv[v] * q.y + w[v] * q.z;
@@ -689,7 +690,7 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int TL = Q * SPLIT;  // lanes per task
   const int R = 64 / TL, lt = lane % TL, lq = lt % Q, half = lt / Q;
-  const float u0f = float(u0), v0f = float(v0);
+  const float u0f = float(u0), v0f = float(v0), w0f = float(d.w0);
   const int K = d.nvis;
   const bool recur = !FP32_PHASE && V > 1 && a.chan_recur != 0;
   for (int task = wave * R + lane / TL; task < nchunks * G; task += W * R) {
@@ -722,7 +723,7 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
         } else {
           du[v] = float(q[0] * s - u0);
           dv[v] = float(q[1] * s - v0);
-          w[v] = float(q[2] * s);
+          w[v] = float(q[2] * s - d.w0);
         }
         if (v == 0 && wave_runs && nv > 1) {  // the step to the next channel
           const double ds = (a.freqs[c + 1] - a.freqs[c]) / kC0;
@@ -740,9 +741,9 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
     const int span = NPIX / G / SPLIT;
     const int lo = g * (NPIX / G) + half * span, hi = lo + span;
     if (wave_runs)
-      degrid_pixels<L, V, FP32_PHASE, true>(y, du, dv, w, sx, sy, sz, a, s_b, s_lmn, lo, hi, u0f, v0f);
+      degrid_pixels<L, V, FP32_PHASE, true>(y, du, dv, w, sx, sy, sz, a, s_b, s_lmn, lo, hi, u0f, v0f, w0f);
     else
-      degrid_pixels<L, V, FP32_PHASE, false>(y, du, dv, w, sx, sy, sz, a, s_b, s_lmn, lo, hi, u0f, v0f);
+      degrid_pixels<L, V, FP32_PHASE, false>(y, du, dv, w, sx, sy, sz, a, s_b, s_lmn, lo, hi, u0f, v0f, w0f);
     if (SPLIT == 2) {
 #pragma unroll
       for (int v = 0; v < V; ++v)
@@ -787,7 +788,8 @@ __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, Degri
     const int row = pix / L, col = pix % L;
 #pragma unroll
     for (int pol = 0; pol < 4; ++pol)
-      sm.sg[SgLayout<L>::idx(pol, pix)] = a.grid_in[(int64_t(pol) * N + d.y0 + row) * N + d.x0 + col];
+      sm.sg[SgLayout<L>::idx(pol, pix)] =
+          a.grid_in[((int64_t(d.layer) * 4 + pol) * N + d.y0 + row) * N + d.x0 + col];
   }
   __syncthreads();
   if constexpr (WIDE && L <= 32) lds_centred_dft_one_thread_per_line<L, NT, true>(sm.sg, sm.tw);
@@ -941,11 +943,13 @@ __global__ void __launch_bounds__(256) adder_kernel(AdderArgs a) {
   constexpr int T = kAdderTile, ROWS = 256 / T, PER = T / ROWS, NPIX = L * L, U = 4;
   const AdderItem it = a.items[blockIdx.x];
   const int pol = blockIdx.y;
-  const int tx = it.tile % a.ntx, ty = it.tile / a.ntx;
+  const int ntile = a.ntx * a.ntx;  // tile ids run over W-layers: layer * ntile + ty * ntx + tx
+  const int layer = it.tile / ntile, tile = it.tile % ntile;
+  const int tx = tile % a.ntx, ty = tile / a.ntx;
   const int N = a.grid_size;
   const int px = threadIdx.x % T, py = threadIdx.x / T;
   const int x = tx * T + px;
-  float2 *gp = a.grid + int64_t(pol) * N * N;
+  float2 *gp = a.grid + (int64_t(layer) * 4 + pol) * N * N;
   float2 acc[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
@@ -998,11 +1002,13 @@ __global__ void __launch_bounds__(256) combine_kernel(AdderArgs a) {
   constexpr int T = kAdderTile, ROWS = 256 / T, PER = T / ROWS;
   const CombineItem it = a.combine[blockIdx.x];
   const int pol = blockIdx.y;
-  const int tx = it.tile % a.ntx, ty = it.tile / a.ntx;
+  const int ntile = a.ntx * a.ntx;
+  const int layer = it.tile / ntile, tile = it.tile % ntile;
+  const int tx = tile % a.ntx, ty = tile / a.ntx;
   const int N = a.grid_size;
   const int px = threadIdx.x % T, py = threadIdx.x / T;
   const int x = tx * T + px;
-  float2 *gp = a.grid + int64_t(pol) * N * N;
+  float2 *gp = a.grid + (int64_t(layer) * 4 + pol) * N * N;
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int y = ty * T + py + k * ROWS;
@@ -1035,7 +1041,8 @@ __global__ void __launch_bounds__(Cfg<L>::NT) splitter_kernel(const DevSubgrid *
     const int pix = threadIdx.x + r * NT;
     const int row = pix / L, col = pix % L;
 #pragma unroll
-    for (int pol = 0; pol < 4; ++pol) o[pol * NPIX + pix] = grid[(int64_t(pol) * N + d.y0 + row) * N + d.x0 + col];
+    for (int pol = 0; pol < 4; ++pol)
+      o[pol * NPIX + pix] = grid[((int64_t(d.layer) * 4 + pol) * N + d.y0 + row) * N + d.x0 + col];
   }
 }
 

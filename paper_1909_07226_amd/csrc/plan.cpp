@@ -28,45 +28,66 @@ inline Box merge(const Box &a, const Box &b) {
 
 struct BaselineGeometry {
   int nt = 0, nch = 0;
-  std::vector<double> x, y, wpix;  // [t * nch + c]
+  double S = 0.0, w_step = 0.0;
+  std::vector<double> x, y, w;  // [t * nch + c]; w in wavelengths
 
   void compute(const double *uvw_bl, const double *freqs, const idg_params &p) {
     nt = p.nr_timesteps;
     nch = p.nr_channels;
+    S = p.image_size;
+    w_step = p.w_step;
     x.resize(size_t(nt) * nch);
     y.resize(x.size());
-    wpix.resize(x.size());
-    const double S = p.image_size;
+    w.resize(x.size());
     const double half_n = p.grid_size / 2.0;
     for (int t = 0; t < nt; ++t) {
       const double *q = uvw_bl + size_t(t) * 3;
       for (int c = 0; c < nch; ++c) {
         const double s = freqs[c] / kSpeedOfLight;
-        const double u = q[0] * s, v = q[1] * s, w = q[2] * s;
+        const double u = q[0] * s, v = q[1] * s;
         double ux = u * S;
         double vy = v * S;
-        double ws = std::fabs(w) * S;
-        ws = ws * S;
         const size_t i = size_t(t) * nch + c;
         x[i] = ux + half_n;
         y[i] = vy + half_n;
-        wpix[i] = std::ceil(ws);
+        w[i] = q[2] * s;
       }
     }
   }
 
-  Box box(int t, int lo, int hi) const {
+  // W-layer of a block of channels [lo, hi) starting at timestep t: floor(w_mid / w_step + 0.5)
+  // of the mid-band w (w is linear in frequency); 0 without layers.
+  int layer(int t, int lo, int hi) const {
+    if (!(w_step > 0.0)) return 0;
     const size_t base = size_t(t) * nch;
-    Box b{x[base + lo], x[base + lo], y[base + lo], y[base + lo], wpix[base + lo]};
+    double mid = w[base + lo] + w[base + hi - 1];
+    mid = mid * 0.5;
+    mid = mid / w_step;
+    return int(std::floor(mid + 0.5));
+  }
+
+  // w-support ceil((|w - w0| * S) * S) of one sample
+  double wsupport(size_t i, double w0) const {
+    double ws = std::fabs(w[i] - w0) * S;
+    ws = ws * S;
+    return std::ceil(ws);
+  }
+
+  Box box(int t, int lo, int hi, double w0) const {
+    const size_t base = size_t(t) * nch;
+    Box b{x[base + lo], x[base + lo], y[base + lo], y[base + lo], wsupport(base + lo, w0)};
     for (int c = lo + 1; c < hi; ++c) {
       b.mnx = std::min(b.mnx, x[base + c]);
       b.mxx = std::max(b.mxx, x[base + c]);
       b.mny = std::min(b.mny, y[base + c]);
       b.mxy = std::max(b.mxy, y[base + c]);
-      b.wpix = std::max(b.wpix, wpix[base + c]);
+      b.wpix = std::max(b.wpix, wsupport(base + c, w0));
     }
     return b;
   }
+
+  // the box of timestep t taken alone (with its own layer)
+  Box alone(int t, int lo, int hi) const { return box(t, lo, hi, double(layer(t, lo, hi)) * w_step); }
 };
 
 inline bool fits(const Box &b, int beta, int L) {
@@ -120,7 +141,7 @@ class Planner {
   void split(int lo, int hi) {
     if (hi - lo > 1) {
       for (int t = 0; t < p_.nr_timesteps; ++t) {
-        if (!fits(geo_.box(t, lo, hi), p_.kernel_size, p_.subgrid_size)) {
+        if (!fits(geo_.alone(t, lo, hi), p_.kernel_size, p_.subgrid_size)) {
           const int mid = lo + (hi - lo) / 2;
           split(lo, mid);
           split(mid, hi);
@@ -135,33 +156,35 @@ class Planner {
     const int nt = p_.nr_timesteps, L = p_.subgrid_size, beta = p_.kernel_size;
     const int tmax = p_.max_timesteps, aslot = p_.aterm_timesteps;
     bool open = false;
-    int t0 = 0, tlast = 0;
+    int t0 = 0, tlast = 0, wl = 0;
     Box cur{};
     for (int t = 0; t < nt; ++t) {
-      const Box bt = geo_.box(t, lo, hi);
+      const int lt = geo_.layer(t, lo, hi);
+      const Box bt = geo_.box(t, lo, hi, double(lt) * geo_.w_step);
       if (!fits(bt, beta, L)) {  // this timestep cannot be gridded even on its own
-        if (open) close(t0, tlast, lo, hi, cur);
+        if (open) close(t0, tlast, lo, hi, cur, wl);
         open = false;
         out_.nr_dropped += count_unflagged(t, t, lo, hi);
         continue;
       }
       if (open) {
-        const Box m = merge(cur, bt);
+        const Box m = merge(cur, geo_.box(t, lo, hi, double(wl) * geo_.w_step));  // the block's own w offset
         if (t - t0 < tmax && t / aslot == t0 / aslot && fits(m, beta, L)) {
           cur = m;
           tlast = t;
           continue;
         }
-        close(t0, tlast, lo, hi, cur);
+        close(t0, tlast, lo, hi, cur, wl);
       }
       open = true;
       t0 = tlast = t;
+      wl = lt;
       cur = bt;
     }
-    if (open) close(t0, tlast, lo, hi, cur);
+    if (open) close(t0, tlast, lo, hi, cur, wl);
   }
 
-  void close(int t0, int t1, int lo, int hi, const Box &b) {
+  void close(int t0, int t1, int lo, int hi, const Box &b, int wlayer) {
     const int kp = count_unflagged(t0, t1, lo, hi);
     if (kp == 0) return;
     const int L = p_.subgrid_size, N = p_.grid_size;
@@ -186,6 +209,7 @@ class Planner {
     r.s1 = baselines_[2 * bl_];
     r.s2 = baselines_[2 * bl_ + 1];
     r.nvis = kp;
+    r.wlayer = wlayer;
     r.vis_offset = out_.nr_gridded;
     for (int t = t0; t <= t1; ++t)
       for (int c = lo; c < hi; ++c)
@@ -227,6 +251,15 @@ int build_plan(const idg_params &p, const int32_t *baselines, const double *uvw,
     out.params = p;
     out.uniform_channels = uniform_spacing(freqs, p.nr_channels);
     Planner(p, baselines, uvw, freqs, flags, out).run();
+    if (!out.subgrids.empty()) {
+      int lo = out.subgrids[0].wlayer, hi = lo;
+      for (const auto &r : out.subgrids) {
+        lo = std::min(lo, r.wlayer);
+        hi = std::max(hi, r.wlayer);
+      }
+      out.wlayer_min = lo;
+      out.nr_wlayers = hi - lo + 1;
+    }
   } catch (const std::bad_alloc &) {
     err = "idg_plan: out of host memory";
     return IDG_ENOMEM;

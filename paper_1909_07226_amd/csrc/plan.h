@@ -14,6 +14,7 @@ constexpr double kSpeedOfLight = 299792458.0;
 // One subgrid: a block of one baseline, timesteps [t0, t0 + nt), channels [c0, c0 + nc).
 struct SubgridRec {
   int32_t bl, t0, nt, c0, nc, x0, y0, slot, s1, s2, nvis;
+  int32_t wlayer;      // W-layer: w offset wlayer * w_step
   int64_t vis_offset;  // first row of this subgrid in HostPlan::samples
 };
 
@@ -24,6 +25,7 @@ struct HostPlan {
   std::vector<int64_t> unplanned;   // flat sample ids (bl * nt + t) * nch + c not gridded
   int64_t nr_gridded = 0, nr_dropped = 0, nr_flagged = 0;
   bool uniform_channels = false;    // channel spacings equal to 1e-9 relative (see uniform_spacing)
+  int32_t wlayer_min = 0, nr_wlayers = 1;  // W-layers in use: grids [nr_wlayers][4][N][N]
 };
 
 // True when every spacing freqs[c + 1] - freqs[c] equals the first one to a

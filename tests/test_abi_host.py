@@ -37,12 +37,12 @@ def test_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(idg._lib.EXPORTED)
-    assert idg.version() == 10100
+    assert idg.version() == 10200
 
 
-def _compare(wl):
-    ref = plan_workload(wl)
-    p = idg.Plan.from_workload(wl)
+def _compare(wl, w_step=0.0):
+    ref = plan_workload(wl, w_step)
+    p = idg.Plan.from_workload(wl, w_step=w_step)
     st = p.stats()
     assert st == dict(nr_subgrids=ref.nr_subgrids, nr_gridded=ref.nr_gridded, nr_dropped=ref.nr_dropped,
                       nr_flagged=ref.nr_flagged)
@@ -68,6 +68,33 @@ def test_plan_parity_hand_cases():
     flags[0, 7:14] = 1
     uvw[0, :, 2] = 0.0
     _compare(make_mini(uvw, N=128, L=16, beta=3, flags=flags))
+
+
+@pytest.mark.parametrize("w_step", [0.7, 4.0])
+def test_plan_parity_w_layers(w_step):
+    # deep w (|w| S^2 up to 40 px at L = 32) across channels: layers, per-timestep layers in the
+    # channel-group step, the block's own offset in the time scan
+    rng = np.random.default_rng(17)
+    uvw = np.zeros((6, 30, 3))
+    t = np.arange(30)
+    for b in range(6):
+        uvw[b, :, 0] = rng.uniform(-30, 30) + rng.uniform(-0.6, 0.6) * t
+        uvw[b, :, 1] = rng.uniform(-30, 30) + rng.uniform(-0.6, 0.6) * t
+        uvw[b, :, 2] = rng.choice([-1, 1]) * (rng.uniform(5, 40) + rng.uniform(0, 0.5) * t)
+    wl = make_mini(uvw, freqs=synth.C0 * (1.0 + 0.05 * np.arange(4)), N=128, L=32, beta=7)
+    p, ref = _compare(wl, w_step)
+    assert p.wlayers() == (ref.wlayer_min, ref.nr_wlayers) and ref.nr_wlayers > 1
+    assert p.shapes()["grid"] == (ref.nr_wlayers, 4, 128, 128)
+
+
+def test_plan_parity_lofar_subset_with_layers():
+    # LOFAR-like geometry on a 4x wider field (S = 0.2): |w| S^2 reaches ~80 pixels without layers
+    import dataclasses
+    wl = synth.make_workload("lofar", with_vis=False)
+    wl = dataclasses.replace(wl, image_size=0.2, baselines=wl.baselines[::64], uvw=wl.uvw[::64, :256])
+    _, ref0 = _compare(wl)
+    _, ref = _compare(wl, 50.0)
+    assert ref.nr_gridded > ref0.nr_gridded and ref.nr_wlayers > 1
 
 
 def test_plan_parity_tiny():
