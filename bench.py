@@ -315,14 +315,21 @@ def main():
         torch.cuda.synchronize()
         idg.profile(True)
         idg.profile_read(reset=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         t0 = time.perf_counter()
-        for _ in range(steps):
+        ev[0].record(stream)
+        for i in range(steps):
             step()
+            ev[i + 1].record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         idg.sync(stream)
         prof = idg.profile_read(reset=True)
         idg.profile(False)
+        per_step = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+        timed.dist = dict(median=round(float(np.median(per_step)), 4),
+                          p90=round(float(np.percentile(per_step, 90)), 4),
+                          min=round(float(per_step.min()), 4), max=round(float(per_step.max()), 4))
         return (t1 - t0) * 1e3 / steps, prof
 
     tune_info = None
@@ -336,6 +343,7 @@ def main():
         plan.set_tuning(adder_chunk=args.adder_chunk)
     log(f"[bench] tuning {plan.get_tuning()}; warmup {args.warmup}, timing {args.steps} steps")
     ms_step, prof = timed(args.steps, args.warmup)
+    step_dist = dict(timed.dist)
     value = nvis / (ms_step * 1e-3) / 1e6
     k = args.steps
     g_ms, g_n = prof["gridder"]
@@ -358,7 +366,8 @@ def main():
     if args.form == "auto":
         plan.set_tuning(form="plain", blocks_per_cu=0, adder_chunk=tuned["adder_chunk"], degrid_shape="standard")
         p_ms, _ = timed(args.steps, 1)
-        plain_form = {"ms_per_step": round(p_ms, 4), "value": round(nvis / (p_ms * 1e-3) / 1e6, 3)}
+        plain_form = {"ms_per_step": round(p_ms, 4), "value": round(nvis / (p_ms * 1e-3) / 1e6, 3),
+                      "step_ms": dict(timed.dist)}
         log(f"[bench] plain form: {plain_form}")
         plan.set_tuning(**tuned)
 
@@ -370,6 +379,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "step_ms": step_dist,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
