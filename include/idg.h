@@ -285,7 +285,9 @@ int idg_split_subgrids(idg_plan_t plan, const idg_cf32 *grid_d, int64_t first, i
  *   image_d   device complex64 [4][N][N], OVERWRITTEN; may be grid_d itself
  *             (in place), must not overlap it otherwise
  * N = grid_size must be a power of two in [64, 16384].  Two passes over the
- * array; N/2 x 8 bytes of twiddles are allocated stream-ordered for the call.
+ * array (three for N >= 2048); N/2 x 8 bytes of twiddles are allocated
+ * stream-ordered for the call, and for an in-place call with N >= 2048 also
+ * 4 N^2 x 8 bytes of scratch.
  * Errors: IDG_EINVAL (size, NULL or partly overlapping buffers), IDG_ENOMEM,
  * IDG_EHIP.
  */

@@ -725,14 +725,18 @@ static int image_transform(const char *fn, bool to_image, const idg_cf32 *src_d,
   int rc = image_args(fn, src_d, N, cl, cm, dst_d);
   if (rc != IDG_OK) return rc;
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  float2 *tw = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&tw), size_t(N) / 2 * sizeof(float2), s), "image twiddles");
   const float2 *in = reinterpret_cast<const float2 *>(src_d);
   float2 *out = reinterpret_cast<float2 *>(dst_d);
+  // twiddles, plus a [4][N][N] intermediate for in-place calls of the four-step form
+  const size_t nscr = idg::image_needs_scratch(N, in, out) ? size_t(4) * N * N : 0;
+  float2 *tw = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&tw), (size_t(N) / 2 + nscr) * sizeof(float2), s),
+          "image scratch");
+  float2 *scr = nscr ? tw + N / 2 : nullptr;
   hipError_t e = idg::launch_image_twiddles(tw, N, s);
   if (e == hipSuccess)
-    e = to_image ? idg::launch_grid_to_image(in, out, N, cl, cm, tw, s)
-                 : idg::launch_image_to_grid(in, out, N, cl, cm, tw, s);
+    e = to_image ? idg::launch_grid_to_image(in, out, N, cl, cm, tw, scr, s)
+                 : idg::launch_image_to_grid(in, out, N, cl, cm, tw, scr, s);
   const hipError_t ef = hipFreeAsync(tw, s);
   if (e != hipSuccess) return hip_fail(e, to_image ? "idg_grid_to_image: launch" : "idg_image_to_grid: launch");
   HIP_TRY(ef, "image twiddles release");
@@ -782,7 +786,7 @@ int idg_wstack_to_image(const idg_cf32 *grids_d, int32_t nr_wlayers, const doubl
   float2 *img = reinterpret_cast<float2 *>(image_d);
   hipError_t e = idg::launch_image_twiddles(tw, N, s);
   for (int j = 0; j < nr_wlayers && e == hipSuccess; ++j) {
-    e = idg::launch_grid_to_image(g + nn * j, scr, N, nullptr, nullptr, tw, s);
+    e = idg::launch_grid_to_image(g + nn * j, scr, N, nullptr, nullptr, tw, nullptr, s);
     if (e == hipSuccess)
       e = idg::launch_wlayer_phase(scr, img, N, image_size, w0s[j], +1, j > 0, corr_l_d, corr_m_d, s);
   }
@@ -810,7 +814,7 @@ int idg_image_to_wstack(const idg_cf32 *image_d, int32_t grid_size, double image
   hipError_t e = idg::launch_image_twiddles(tw, N, s);
   for (int j = 0; j < nr_wlayers && e == hipSuccess; ++j) {
     e = idg::launch_wlayer_phase(img, scr, N, image_size, w0s[j], -1, false, corr_l_d, corr_m_d, s);
-    if (e == hipSuccess) e = idg::launch_image_to_grid(scr, g + nn * j, N, nullptr, nullptr, tw, s);
+    if (e == hipSuccess) e = idg::launch_image_to_grid(scr, g + nn * j, N, nullptr, nullptr, tw, nullptr, s);
   }
   const hipError_t ef = hipFreeAsync(scr, s);
   if (e != hipSuccess) return hip_fail(e, "idg_image_to_wstack: launch");

@@ -134,7 +134,15 @@ __device__ __forceinline__ void lds_groups(float2 *s, const float2 *__restrict__
 // of the [4][N][N] array; out may equal in (a workgroup reads all its elements
 // before its first write; workgroups are disjoint).  SCALE 1 divides the input
 // by sr[row] sc[col], SCALE 2 the output.
-template <int N, int C, bool COLS, int SIGN, int SCALE>
+// Four-step split of a column transform: N = N1 N2 with N1 = 2^ceil(log2 N / 2).
+template <int N>
+constexpr int four_step_n1() {
+  return 1 << ((ilog2c(N) + 1) / 2);
+}
+
+// GATHER (row pass only): output row p = n1 + N1 n2 takes input row N2 n1 + n2,
+// the order the four-step column transform starts from.
+template <int N, int C, bool COLS, int SIGN, int SCALE, bool GATHER = false>
 __global__ void __launch_bounds__(fft_threads(N * C))
     fft_batch_kernel(const float2 *in, float2 *out, const float2 *__restrict__ tw, const float *__restrict__ sr,
                      const float *__restrict__ sc) {
@@ -151,6 +159,15 @@ __global__ void __launch_bounds__(fft_threads(N * C))
   auto gofs = [&](int i, int c) -> int64_t {
     return COLS ? pbase + int64_t(i) * N + b0 + c : pbase + int64_t(b0 + c) * N + i;
   };
+  auto gofs_in = [&](int i, int c) -> int64_t {
+    if constexpr (GATHER) {
+      constexpr int N1 = four_step_n1<N>(), N2 = N / N1;
+      const int p = b0 + c;
+      return pbase + int64_t(N2 * (p % N1) + p / N1) * N + i;
+    } else {
+      return gofs(i, c);
+    }
+  };
   auto inv_corr = [&](int i, int c) -> float {
     return COLS ? 1.0f / (sr[i] * sc[b0 + c]) : 1.0f / (sr[b0 + c] * sc[i]);
   };
@@ -164,7 +181,7 @@ __global__ void __launch_bounds__(fft_threads(N * C))
       const int w = tid + k * NT;
       const int c = COLS ? w % C : w / HM, lo = COLS ? w / C : w % HM;
 #pragma unroll
-      for (int m = 0; m < 8; ++m) v[k][m] = in[gofs(lo + m * HM, c)];
+      for (int m = 0; m < 8; ++m) v[k][m] = in[gofs_in(lo + m * HM, c)];
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -205,6 +222,124 @@ __global__ void __launch_bounds__(fft_threads(N * C))
     if constexpr (SCALE == 2) f *= inv_corr(kk, c);
     out[gofs(kk, c)] = make_float2(v.x * f, v.y * f);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Four-step column transform, N = N1 N2 (N >= 2048).  After the gathered row
+// pass, position p = n1 + N1 n2 of a column holds its element N2 n1 + n2.
+//   step A: for each n2, the length-N1 DFT over the N1 consecutive rows N1 n2 + n1,
+//           times exp(SIGN 2 pi i n2 k1 / N), back into rows N1 n2 + k1;
+//   step B: for each k1, the length-N2 DFT over rows k1 + N1 n2, into rows k1 + N1 k2,
+//           which is output row k = k1 + N1 k2: natural order, in place.
+// The centring signs are (-1)^n = (-1)^n2 (applied on step A's input) and
+// (-1)^k = (-1)^k1 (on step B's output).  A workgroup takes 16 adjacent columns
+// (128-byte rows) and 128 / T sub-transforms of length T: 2048 elements, 18 KiB
+// of LDS, 256 threads.  With GATHER, step A reads the element from its natural
+// row N2 n1 + n2 instead (image -> grid, whose first pass is the column transform).
+constexpr int kSubCols = 16, kSubElems = 128, kSubThreads = 256;
+
+__device__ __forceinline__ int sub_lds(int i, int c) { return kSubCols * (i + (i >> 3)) + c; }
+
+template <int NTAB, int SIGN, int H, int R>
+__device__ __forceinline__ void sub_group(float2 *s, const float2 *__restrict__ tw, int tid) {
+  constexpr int E = 1 << R, HM = H >> (R - 1), NSET = kSubElems / E, PER = NSET * kSubCols / kSubThreads;
+  constexpr int LH = ilog2c(H), LHM = ilog2c(HM);
+  static_assert(PER >= 1, "work split");
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int w = tid + k * kSubThreads;
+    const int c = w % kSubCols, set = w / kSubCols;
+    const int lo = set & (HM - 1), ib = lo + ((set >> LHM) << (LH + 1));
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = s[sub_lds(ib + m * HM, c)];
+    dif_set<NTAB, R, SIGN>(v, lo, HM, tw);
+#pragma unroll
+    for (int m = 0; m < E; ++m) s[sub_lds(ib + m * HM, c)] = v[m];
+  }
+  __syncthreads();
+}
+
+template <int NTAB, int SIGN, int H>
+__device__ __forceinline__ void sub_groups(float2 *s, const float2 *__restrict__ tw, int tid) {
+  if constexpr (H >= 4) {
+    sub_group<NTAB, SIGN, H, 3>(s, tw, tid);
+    sub_groups<NTAB, SIGN, H / 8>(s, tw, tid);
+  } else if constexpr (H == 2) {
+    sub_group<NTAB, SIGN, 2, 2>(s, tw, tid);
+  } else if constexpr (H == 1) {
+    sub_group<NTAB, SIGN, 1, 1>(s, tw, tid);
+  }
+}
+
+template <int N, bool STEP_B, bool GATHER, int SIGN, int SCALE>
+__global__ void __launch_bounds__(kSubThreads) fft_sub_kernel(const float2 *in, float2 *out,
+                                                              const float2 *__restrict__ tw,
+                                                              const float *__restrict__ sr,
+                                                              const float *__restrict__ sc) {
+  constexpr int N1 = four_step_n1<N>(), N2 = N / N1;
+  constexpr int T = STEP_B ? N2 : N1, GB = kSubElems / T, NBLK = STEP_B ? N1 : N2;
+  constexpr int NGRP = NBLK / GB, NCG = N / kSubCols;
+  constexpr int lt = ilog2c(T);
+  static_assert(GB >= 1 && NBLK % GB == 0, "sub-transform grouping");
+  __shared__ float2 s[kSubCols * (kSubElems + kSubElems / 8)];
+  const int tid = threadIdx.x;
+  const int bg = blockIdx.x % NGRP, rest = blockIdx.x / NGRP;
+  const int x0 = (rest % NCG) * kSubCols;
+  const int64_t pbase = int64_t(rest / NCG) * N * N;
+  constexpr int PER = kSubElems * kSubCols / kSubThreads;
+  float2 v[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {  // loads first, for bytes in flight
+    const int e = tid + j * kSubThreads, c = e % kSubCols, rr = e / kSubCols;
+    const int blk = bg * GB + rr / T, i = rr % T;
+    const int row = STEP_B ? blk + N1 * i : (GATHER ? N2 * i + blk : N1 * blk + i);
+    v[j] = in[pbase + int64_t(row) * N + x0 + c];
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + j * kSubThreads, c = e % kSubCols, rr = e / kSubCols;
+    const int blk = bg * GB + rr / T, i = rr % T;
+    float f = (!STEP_B && (blk & 1)) ? -1.0f : 1.0f;
+    if constexpr (SCALE == 1) {
+      const int row = STEP_B ? blk + N1 * i : (GATHER ? N2 * i + blk : N1 * blk + i);
+      f /= sr[row] * sc[x0 + c];
+    }
+    s[sub_lds(rr, c)] = make_float2(v[j].x * f, v[j].y * f);
+  }
+  __syncthreads();
+  sub_groups<N, SIGN, T / 2>(s, tw, tid);
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + j * kSubThreads, c = e % kSubCols, rr = e / kSubCols;
+    const int blk = bg * GB + rr / T, k = int(__brev(unsigned(rr % T)) >> (32 - lt));
+    float2 x = s[sub_lds(rr, c)];
+    int row;
+    if constexpr (STEP_B) {
+      row = blk + N1 * k;
+      float f = (blk & 1) ? -1.0f : 1.0f;
+      if constexpr (SCALE == 2) f /= sr[row] * sc[x0 + c];
+      x = make_float2(x.x * f, x.y * f);
+    } else {
+      row = N1 * blk + k;
+      const int m = (blk * k) & (N - 1);  // exp(SIGN 2 pi i m / N) from the half table
+      float2 w = tw[m & (N / 2 - 1)];
+      if (m >= N / 2) w = make_float2(-w.x, -w.y);
+      if (SIGN > 0) w.y = -w.y;
+      x = fmul(x, w);
+    }
+    out[pbase + int64_t(row) * N + x0 + c] = x;
+  }
+}
+
+template <int N, bool STEP_B, bool GATHER, int SIGN, int SCALE>
+static hipError_t launch_fft_sub(const float2 *in, float2 *out, const float2 *tw, const float *sr, const float *sc,
+                                 hipStream_t st) {
+  constexpr int N1 = four_step_n1<N>(), N2 = N / N1, T = STEP_B ? N2 : N1, NBLK = STEP_B ? N1 : N2;
+  constexpr int64_t blocks = int64_t(4) * (N / kSubCols) * (NBLK / (kSubElems / T));
+  hipLaunchKernelGGL((fft_sub_kernel<N, STEP_B, GATHER, SIGN, SCALE>), dim3(unsigned(blocks)), dim3(kSubThreads), 0,
+                     st, in, out, tw, sr, sc);
+  return hipGetLastError();
 }
 
 // W-layers: out[pol][y][x] (= or +=) in[pol][y][x] exp(SIGN 2 pi i w0 n'(l_x, m_y)) [/ (cm[y] cl[x])],
@@ -280,16 +415,24 @@ constexpr int col_batch() {
   return kColElems / N < 1 ? 1 : (kColElems / N < 16 ? kColElems / N : 16);
 }
 
-template <int N, bool COLS, int SIGN, int SCALE>
+template <int N, bool COLS, int SIGN, int SCALE, bool GATHER = false>
 static hipError_t launch_fft_batch(const float2 *in, float2 *out, const float2 *tw, const float *sr, const float *sc,
                                    hipStream_t st) {
   constexpr int C = COLS ? col_batch<N>() : row_batch<N>();
   using S = FftShape<N, C, COLS>;
   static_assert(S::LDS * sizeof(float2) <= 160 * 1024, "LDS");
   static_assert((N / 8) * C % S::NT == 0 && (N / 2) * C % S::NT == 0, "work split");
-  hipLaunchKernelGGL((fft_batch_kernel<N, C, COLS, SIGN, SCALE>), dim3(4 * N / C), dim3(S::NT), 0, st, in, out, tw,
-                     sr, sc);
+  static_assert(!GATHER || (!COLS && C == 1), "gathered rows: one row per workgroup");
+  hipLaunchKernelGGL((fft_batch_kernel<N, C, COLS, SIGN, SCALE, GATHER>), dim3(4 * N / C), dim3(S::NT), 0, st, in,
+                     out, tw, sr, sc);
   return hipGetLastError();
+}
+
+// The column transform takes the four-step form where whole-column blocks of
+// LDS would read fewer than 16 columns (128 bytes) per row.
+template <int N>
+constexpr bool use_four_step() {
+  return col_batch<N>() < kSubCols && N >= 2048;
 }
 
 #define IDG_DISPATCH_N(N, ...)                                    \
@@ -312,25 +455,60 @@ hipError_t launch_image_twiddles(float2 *tw, int N, hipStream_t s) {
   return hipGetLastError();
 }
 
+bool image_needs_scratch(int N, const void *in, const void *out) {
+  bool four = false;
+  switch (N) {
+    case 2048: four = use_four_step<2048>(); break;
+    case 4096: four = use_four_step<4096>(); break;
+    case 8192: four = use_four_step<8192>(); break;
+    case 16384: four = use_four_step<16384>(); break;
+    default: break;
+  }
+  return four && in == out;
+}
+
 hipError_t launch_grid_to_image(const float2 *grid, float2 *image, int N, const float *corr_l, const float *corr_m,
-                                const float2 *tw, hipStream_t s) {
+                                const float2 *tw, float2 *scratch, hipStream_t s) {
   hipError_t e = hipSuccess;
   IDG_DISPATCH_N(N, {
-    e = launch_fft_batch<NN, false, 1, 0>(grid, image, tw, nullptr, nullptr, s);
-    if (e == hipSuccess)
-      e = corr_l ? launch_fft_batch<NN, true, 1, 2>(image, image, tw, corr_m, corr_l, s)
-                 : launch_fft_batch<NN, true, 1, 0>(image, image, tw, nullptr, nullptr, s);
+    if constexpr (use_four_step<NN>()) {
+      // rows gathered into the four-step order (they cross workgroups: in place goes through
+      // scratch), step A in place, step B into the image
+      float2 *mid = (grid == image) ? scratch : image;
+      if (!mid) return hipErrorInvalidValue;
+      e = launch_fft_batch<NN, false, 1, 0, true>(grid, mid, tw, nullptr, nullptr, s);
+      if (e == hipSuccess) e = launch_fft_sub<NN, false, false, 1, 0>(mid, mid, tw, nullptr, nullptr, s);
+      if (e == hipSuccess)
+        e = corr_l ? launch_fft_sub<NN, true, false, 1, 2>(mid, image, tw, corr_m, corr_l, s)
+                   : launch_fft_sub<NN, true, false, 1, 0>(mid, image, tw, nullptr, nullptr, s);
+    } else {
+      e = launch_fft_batch<NN, false, 1, 0>(grid, image, tw, nullptr, nullptr, s);
+      if (e == hipSuccess)
+        e = corr_l ? launch_fft_batch<NN, true, 1, 2>(image, image, tw, corr_m, corr_l, s)
+                   : launch_fft_batch<NN, true, 1, 0>(image, image, tw, nullptr, nullptr, s);
+    }
   });
   return e;
 }
 
 hipError_t launch_image_to_grid(const float2 *image, float2 *grid, int N, const float *corr_l, const float *corr_m,
-                                const float2 *tw, hipStream_t s) {
+                                const float2 *tw, float2 *scratch, hipStream_t s) {
   hipError_t e = hipSuccess;
   IDG_DISPATCH_N(N, {
-    e = corr_l ? launch_fft_batch<NN, true, -1, 1>(image, grid, tw, corr_m, corr_l, s)
-               : launch_fft_batch<NN, true, -1, 0>(image, grid, tw, nullptr, nullptr, s);
-    if (e == hipSuccess) e = launch_fft_batch<NN, false, -1, 0>(grid, grid, tw, nullptr, nullptr, s);
+    if constexpr (use_four_step<NN>()) {
+      // step A gathering from the image's natural rows (across workgroups: in place goes
+      // through scratch), step B in place, then the rows into the grid
+      float2 *mid = (grid == image) ? scratch : grid;
+      if (!mid) return hipErrorInvalidValue;
+      e = corr_l ? launch_fft_sub<NN, false, true, -1, 1>(image, mid, tw, corr_m, corr_l, s)
+                 : launch_fft_sub<NN, false, true, -1, 0>(image, mid, tw, nullptr, nullptr, s);
+      if (e == hipSuccess) e = launch_fft_sub<NN, true, false, -1, 0>(mid, mid, tw, nullptr, nullptr, s);
+      if (e == hipSuccess) e = launch_fft_batch<NN, false, -1, 0>(mid, grid, tw, nullptr, nullptr, s);
+    } else {
+      e = corr_l ? launch_fft_batch<NN, true, -1, 1>(image, grid, tw, corr_m, corr_l, s)
+                 : launch_fft_batch<NN, true, -1, 0>(image, grid, tw, nullptr, nullptr, s);
+      if (e == hipSuccess) e = launch_fft_batch<NN, false, -1, 0>(grid, grid, tw, nullptr, nullptr, s);
+    }
   });
   return e;
 }

@@ -91,13 +91,16 @@ hipError_t launch_zero_samples(const int64_t *ids, int64_t n, float2 *vis, hipSt
 // master grid <-> image (image.hip)
 bool image_size_supported(int N);
 hipError_t launch_image_twiddles(float2 *tw, int N, hipStream_t s);
-// the two-pass 2-D transforms of the [4][N][N] array (image.hip), N a power of two in [64, 16384]:
-// image = T(grid) / (corr_m[y] corr_l[x]), grid = T^H(image / (corr_m[y] corr_l[x])); corrections both
-// NULL or both set; in place allowed (image == grid); tw from launch_image_twiddles
+// The 2-D transforms of the [4][N][N] array (image.hip), N a power of two in [64, 16384]:
+// image = T(grid) / (corr_m[y] corr_l[x]), grid = T^H(image / (corr_m[y] corr_l[x])); corrections
+// both NULL or both set; tw from launch_image_twiddles.  In place (image == grid) needs a
+// [4][N][N] scratch when image_needs_scratch says so (the four-step form, N >= 2048); scratch is
+// otherwise unused and may be NULL.
+bool image_needs_scratch(int N, const void *in, const void *out);
 hipError_t launch_grid_to_image(const float2 *grid, float2 *image, int N, const float *corr_l, const float *corr_m,
-                                const float2 *tw, hipStream_t s);
+                                const float2 *tw, float2 *scratch, hipStream_t s);
 hipError_t launch_image_to_grid(const float2 *image, float2 *grid, int N, const float *corr_l, const float *corr_m,
-                                const float2 *tw, hipStream_t s);
+                                const float2 *tw, float2 *scratch, hipStream_t s);
 
 // out (= or +=) in * exp(sign 2 pi i w0 n'(l, m)) [/ (corr_m[y] corr_l[x])] over [4][N][N]
 hipError_t launch_wlayer_phase(const float2 *in, float2 *out, int N, double S, double w0, int sign, bool accumulate,
