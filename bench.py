@@ -246,6 +246,62 @@ def serving_leg(lofar_wl, lofar_dev, n_jobs, log):
     return out
 
 
+def wstack_leg(idg, torch, wl, tuned, log, image_size=0.2, w_step=200.0, steps=3):
+    """W-layers at scale: the workload's geometry on a wider field (S = image_size), where |w| S^2
+    exceeds what a subgrid can hold.  Plans without and with layers (spacing w_step wavelengths),
+    grid + degrid MVis/s of the layered plan, and the W-stacked transform of all layer grids."""
+    import dataclasses
+    wide = dataclasses.replace(wl, image_size=image_size)
+    out = {"image_size": image_size, "w_step": w_step}
+    out["unlayered"] = idg.Plan.from_workload(wide).stats()
+    plan = idg.Plan.from_workload(wide, w_step=w_step)
+    nsub = plan.stats()["nr_subgrids"]
+    plan = idg.Plan.from_workload(wide, w_step=w_step,
+                                  scratch_bytes=nsub * 4 * wide.subgrid_size ** 2 * 8 + (1 << 20))
+    plan.set_tuning(**tuned)
+    st = plan.stats()
+    lo, nl = plan.wlayers()
+    N = wide.grid_size
+    dev = "cuda"
+    uvw, freqs = torch.from_numpy(wide.uvw).to(dev), torch.from_numpy(wide.freqs).to(dev)
+    vis, aterms = torch.from_numpy(wide.vis).to(dev), torch.from_numpy(wide.aterms).to(dev)
+    taper = torch.from_numpy(wide.taper).to(dev)
+    grids = torch.zeros(plan.shapes()["grid"], dtype=torch.complex64, device=dev)
+    vis_out = torch.empty_like(vis)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        grids.zero_()
+        idg.grid(plan, uvw, freqs, vis, aterms, taper, grids, stream)
+        idg.degrid(plan, uvw, freqs, grids, aterms, taper, vis_out, stream)
+
+    step()
+    idg.sync(stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    img = torch.empty((4, N, N), dtype=torch.complex64, device=dev)
+    w0s = plan.w_offsets()
+    idg.wstack_to_image(grids, w0s, image_size, None, None, img, stream)
+    e0.record(stream)
+    idg.wstack_to_image(grids, w0s, image_size, None, None, img, stream)
+    e1.record(stream)
+    e1.synchronize()
+    ti = e0.elapsed_time(e1)
+    out.update(layered=st, wlayer_min=lo, nr_wlayers=nl, grid_gb=round(nl * 4 * N * N * 8 / 1e9, 2),
+               ms_per_step=round(ms, 3), mvis_s=round(st["nr_gridded"] / (ms * 1e-3) / 1e6, 1),
+               wstack_to_image_ms=round(ti, 3), per_layer_ms=round(ti / nl, 3))
+    log(f"[bench] W-layers (S = {image_size}, w_step = {w_step}): {nl} layers, gridded {st['nr_gridded']} "
+        f"(without layers {out['unlayered']['nr_gridded']}); grid+degrid {ms:.2f} ms = {out['mvis_s']} MVis/s; "
+        f"W-stacked image {ti:.2f} ms ({ti / nl:.3f} ms per layer)")
+    del grids, img
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,6 +318,7 @@ def main():
                     help="degridder task shape when --form is given (autotuned otherwise)")
     ap.add_argument("--adder-chunk", type=int, default=0, help="adder: longest tile-list run per workgroup (0 = 256)")
     ap.add_argument("--serve-jobs", type=int, default=400, help="jobs in the serving trace (0 = skip serving)")
+    ap.add_argument("--no-wstack", action="store_true", help="skip the W-layer leg (wider field, layered plan)")
     ap.add_argument("--scratch-gb", type=float, default=0.0,
                     help="subgrid scratch budget in GB (0 = enough for the whole plan: one gridder launch)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -408,6 +465,8 @@ def main():
         "cpu_baseline": None,
     }
     result["hbm_stages"] = hbm_stages(idg, torch, plan, grid, stream, a_ms / k, log)
+    if not args.no_wstack and args.workload == "lofar":
+        result["wstack"] = wstack_leg(idg, torch, wl, tuned, log)
     if args.serve_jobs > 0 and args.workload == "lofar":
         result["serving"] = serving_leg(wl, dict(uvw=uvw, freqs=freqs, vis=vis, aterms=aterms, taper=taper),
                                         args.serve_jobs, log)
