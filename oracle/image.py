@@ -112,3 +112,25 @@ def image_to_wstack(image, w0s, S, corr_l, corr_m):
     ones = np.ones(N)
     x = im / np.outer(np.asarray(corr_m, np.float64), np.asarray(corr_l, np.float64))
     return np.stack([image_to_grid(np.exp(-2j * np.pi * float(w0) * n1) * x, ones, ones) for w0 in w0s])
+
+
+def wstack_to_image_at(grids, w0s, S, xs, ys, corr_l, corr_m):
+    """image[:, ys[i], xs[i]] of wstack_to_image, one pixel at a time."""
+    g = np.asarray(grids)
+    N = g.shape[-1]
+    n1 = nprime_image(N, S)[np.asarray(ys), np.asarray(xs)]
+    ones = np.ones(N)
+    out = sum(np.exp(2j * np.pi * float(w0) * n1)[None, :] * grid_to_image_at(g[j], xs, ys, ones, ones)
+              for j, w0 in enumerate(w0s))
+    cl, cm = np.asarray(corr_l, np.float64), np.asarray(corr_m, np.float64)
+    return out / (cm[np.asarray(ys)] * cl[np.asarray(xs)])[None, :]
+
+
+def image_to_wstack_at(image, w0s, S, us, vs, corr_l, corr_m):
+    """grids[:, :, vs[i], us[i]] of image_to_wstack ([layers, 4, len(us)]), one cell at a time."""
+    im = np.asarray(image)
+    N = im.shape[-1]
+    n1 = nprime_image(N, S)
+    ones = np.ones(N)
+    x = im / np.outer(np.asarray(corr_m, np.float64), np.asarray(corr_l, np.float64))
+    return np.stack([image_to_grid_at(np.exp(-2j * np.pi * float(w0) * n1) * x, us, vs, ones, ones) for w0 in w0s])

@@ -785,11 +785,8 @@ int idg_wstack_to_image(const idg_cf32 *grids_d, int32_t nr_wlayers, const doubl
   const float2 *g = reinterpret_cast<const float2 *>(grids_d);
   float2 *img = reinterpret_cast<float2 *>(image_d);
   hipError_t e = idg::launch_image_twiddles(tw, N, s);
-  for (int j = 0; j < nr_wlayers && e == hipSuccess; ++j) {
-    e = idg::launch_grid_to_image(g + nn * j, scr, N, nullptr, nullptr, tw, nullptr, s);
-    if (e == hipSuccess)
-      e = idg::launch_wlayer_phase(scr, img, N, image_size, w0s[j], +1, j > 0, corr_l_d, corr_m_d, s);
-  }
+  for (int j = 0; j < nr_wlayers && e == hipSuccess; ++j)
+    e = idg::launch_wlayer_to_image(g + nn * j, img, scr, N, image_size, w0s[j], j > 0, corr_l_d, corr_m_d, tw, s);
   const hipError_t ef = hipFreeAsync(scr, s);
   if (e != hipSuccess) return hip_fail(e, "idg_wstack_to_image: launch");
   HIP_TRY(ef, "idg_wstack_to_image: scratch release");
@@ -812,10 +809,8 @@ int idg_image_to_wstack(const idg_cf32 *image_d, int32_t grid_size, double image
   const float2 *img = reinterpret_cast<const float2 *>(image_d);
   float2 *g = reinterpret_cast<float2 *>(grids_d);
   hipError_t e = idg::launch_image_twiddles(tw, N, s);
-  for (int j = 0; j < nr_wlayers && e == hipSuccess; ++j) {
-    e = idg::launch_wlayer_phase(img, scr, N, image_size, w0s[j], -1, false, corr_l_d, corr_m_d, s);
-    if (e == hipSuccess) e = idg::launch_image_to_grid(scr, g + nn * j, N, nullptr, nullptr, tw, nullptr, s);
-  }
+  for (int j = 0; j < nr_wlayers && e == hipSuccess; ++j)
+    e = idg::launch_image_to_wlayer(img, g + nn * j, scr, N, image_size, w0s[j], corr_l_d, corr_m_d, tw, s);
   const hipError_t ef = hipFreeAsync(scr, s);
   if (e != hipSuccess) return hip_fail(e, "idg_image_to_wstack: launch");
   HIP_TRY(ef, "idg_image_to_wstack: scratch release");

@@ -236,6 +236,9 @@ __global__ void __launch_bounds__(fft_threads(N * C))
 // (128-byte rows) and 128 / T sub-transforms of length T: 2048 elements, 18 KiB
 // of LDS, 256 threads.  With GATHER, step A reads the element from its natural
 // row N2 n1 + n2 instead (image -> grid, whose first pass is the column transform).
+// SCALE 1 / 2 divide the input / output by the correction; SCALE 3 applies a
+// W-layer's exp(SIGN 2 pi i w0 n'(l, m)) (and the correction, when given) to
+// step A's input or step B's output, which then adds into `out` when acc is set.
 constexpr int kSubCols = 16, kSubElems = 128, kSubThreads = 256;
 
 __device__ __forceinline__ int sub_lds(int i, int c) { return kSubCols * (i + (i >> 3)) + c; }
@@ -272,11 +275,24 @@ __device__ __forceinline__ void sub_groups(float2 *s, const float2 *__restrict__
   }
 }
 
+// exp(SIGN 2 pi i w0 n'(l_x, m_y)) from float64, n' = sqrt(1 - l^2 - m^2) - 1 (0 under the root
+// outside the unit circle), l_x = (x - N/2) S / N
+template <int SIGN>
+__device__ __forceinline__ float2 wlayer_phasor(int x, int y, int N, double S, double w0) {
+  const double l = double(x - N / 2) * S / double(N), m = double(y - N / 2) * S / double(N);
+  double ph = w0 * (sqrt(fmax(0.0, 1.0 - l * l - m * m)) - 1.0);
+  ph -= floor(ph);
+  double sn, cs;
+  sincospi(2.0 * ph, &sn, &cs);
+  return make_float2(float(cs), float(SIGN > 0 ? sn : -sn));
+}
+
 template <int N, bool STEP_B, bool GATHER, int SIGN, int SCALE>
 __global__ void __launch_bounds__(kSubThreads) fft_sub_kernel(const float2 *in, float2 *out,
                                                               const float2 *__restrict__ tw,
                                                               const float *__restrict__ sr,
-                                                              const float *__restrict__ sc) {
+                                                              const float *__restrict__ sc, double S, double w0,
+                                                              int acc) {
   constexpr int N1 = four_step_n1<N>(), N2 = N / N1;
   constexpr int T = STEP_B ? N2 : N1, GB = kSubElems / T, NBLK = STEP_B ? N1 : N2;
   constexpr int NGRP = NBLK / GB, NCG = N / kSubCols;
@@ -301,9 +317,11 @@ __global__ void __launch_bounds__(kSubThreads) fft_sub_kernel(const float2 *in, 
     const int e = tid + j * kSubThreads, c = e % kSubCols, rr = e / kSubCols;
     const int blk = bg * GB + rr / T, i = rr % T;
     float f = (!STEP_B && (blk & 1)) ? -1.0f : 1.0f;
-    if constexpr (SCALE == 1) {
-      const int row = STEP_B ? blk + N1 * i : (GATHER ? N2 * i + blk : N1 * blk + i);
-      f /= sr[row] * sc[x0 + c];
+    const int row = STEP_B ? blk + N1 * i : (GATHER ? N2 * i + blk : N1 * blk + i);
+    if constexpr (SCALE == 1) f /= sr[row] * sc[x0 + c];
+    if constexpr (SCALE == 3 && !STEP_B) {
+      if (sr) f /= sr[row] * sc[x0 + c];
+      v[j] = fmul(v[j], wlayer_phasor<SIGN>(x0 + c, row, N, S, w0));
     }
     s[sub_lds(rr, c)] = make_float2(v[j].x * f, v[j].y * f);
   }
@@ -319,7 +337,15 @@ __global__ void __launch_bounds__(kSubThreads) fft_sub_kernel(const float2 *in, 
       row = blk + N1 * k;
       float f = (blk & 1) ? -1.0f : 1.0f;
       if constexpr (SCALE == 2) f /= sr[row] * sc[x0 + c];
+      if constexpr (SCALE == 3) {
+        if (sr) f /= sr[row] * sc[x0 + c];
+        x = fmul(x, wlayer_phasor<SIGN>(x0 + c, row, N, S, w0));
+      }
       x = make_float2(x.x * f, x.y * f);
+      if (SCALE == 3 && acc) {
+        const float2 o = out[pbase + int64_t(row) * N + x0 + c];
+        x = make_float2(o.x + x.x, o.y + x.y);
+      }
     } else {
       row = N1 * blk + k;
       const int m = (blk * k) & (N - 1);  // exp(SIGN 2 pi i m / N) from the half table
@@ -334,11 +360,11 @@ __global__ void __launch_bounds__(kSubThreads) fft_sub_kernel(const float2 *in, 
 
 template <int N, bool STEP_B, bool GATHER, int SIGN, int SCALE>
 static hipError_t launch_fft_sub(const float2 *in, float2 *out, const float2 *tw, const float *sr, const float *sc,
-                                 hipStream_t st) {
+                                 hipStream_t st, double S = 0.0, double w0 = 0.0, bool acc = false) {
   constexpr int N1 = four_step_n1<N>(), N2 = N / N1, T = STEP_B ? N2 : N1, NBLK = STEP_B ? N1 : N2;
   constexpr int64_t blocks = int64_t(4) * (N / kSubCols) * (NBLK / (kSubElems / T));
   hipLaunchKernelGGL((fft_sub_kernel<N, STEP_B, GATHER, SIGN, SCALE>), dim3(unsigned(blocks)), dim3(kSubThreads), 0,
-                     st, in, out, tw, sr, sc);
+                     st, in, out, tw, sr, sc, S, w0, int(acc));
   return hipGetLastError();
 }
 
@@ -508,6 +534,42 @@ hipError_t launch_image_to_grid(const float2 *image, float2 *grid, int N, const 
       e = corr_l ? launch_fft_batch<NN, true, -1, 1>(image, grid, tw, corr_m, corr_l, s)
                  : launch_fft_batch<NN, true, -1, 0>(image, grid, tw, nullptr, nullptr, s);
       if (e == hipSuccess) e = launch_fft_batch<NN, false, -1, 0>(grid, grid, tw, nullptr, nullptr, s);
+    }
+  });
+  return e;
+}
+
+hipError_t launch_wlayer_to_image(const float2 *grid, float2 *image, float2 *scratch, int N, double S, double w0,
+                                  bool accumulate, const float *corr_l, const float *corr_m, const float2 *tw,
+                                  hipStream_t s) {
+  hipError_t e = hipSuccess;
+  IDG_DISPATCH_N(N, {
+    if constexpr (use_four_step<NN>()) {
+      // gathered rows and step A in scratch; step B applies the layer's phase and adds into the image
+      e = launch_fft_batch<NN, false, 1, 0, true>(grid, scratch, tw, nullptr, nullptr, s);
+      if (e == hipSuccess) e = launch_fft_sub<NN, false, false, 1, 0>(scratch, scratch, tw, nullptr, nullptr, s);
+      if (e == hipSuccess)
+        e = launch_fft_sub<NN, true, false, 1, 3>(scratch, image, tw, corr_m, corr_l, s, S, w0, accumulate);
+    } else {
+      e = launch_grid_to_image(grid, scratch, N, nullptr, nullptr, tw, nullptr, s);
+      if (e == hipSuccess) e = launch_wlayer_phase(scratch, image, N, S, w0, +1, accumulate, corr_l, corr_m, s);
+    }
+  });
+  return e;
+}
+
+hipError_t launch_image_to_wlayer(const float2 *image, float2 *grid, float2 *scratch, int N, double S, double w0,
+                                  const float *corr_l, const float *corr_m, const float2 *tw, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  IDG_DISPATCH_N(N, {
+    if constexpr (use_four_step<NN>()) {
+      // step A gathers from the image with the layer's phase; step B and the rows in the layer grid
+      e = launch_fft_sub<NN, false, true, -1, 3>(image, grid, tw, corr_m, corr_l, s, S, w0, false);
+      if (e == hipSuccess) e = launch_fft_sub<NN, true, false, -1, 0>(grid, grid, tw, nullptr, nullptr, s);
+      if (e == hipSuccess) e = launch_fft_batch<NN, false, -1, 0>(grid, grid, tw, nullptr, nullptr, s);
+    } else {
+      e = launch_wlayer_phase(image, scratch, N, S, w0, -1, false, corr_l, corr_m, s);
+      if (e == hipSuccess) e = launch_image_to_grid(scratch, grid, N, nullptr, nullptr, tw, nullptr, s);
     }
   });
   return e;

@@ -106,4 +106,13 @@ hipError_t launch_image_to_grid(const float2 *image, float2 *grid, int N, const 
 hipError_t launch_wlayer_phase(const float2 *in, float2 *out, int N, double S, double w0, int sign, bool accumulate,
                                const float *corr_l, const float *corr_m, hipStream_t s);
 
+// One W-layer of the W-stacked image steps: image (= or +=) T(grid) exp(+2 pi i w0 n') / corr, and
+// grid = T^H(image exp(-2 pi i w0 n') / corr).  scratch: [4][N][N] (the image direction always uses
+// it; the grid direction only below the four-step form).
+hipError_t launch_wlayer_to_image(const float2 *grid, float2 *image, float2 *scratch, int N, double S, double w0,
+                                  bool accumulate, const float *corr_l, const float *corr_m, const float2 *tw,
+                                  hipStream_t s);
+hipError_t launch_image_to_wlayer(const float2 *image, float2 *grid, float2 *scratch, int N, double S, double w0,
+                                  const float *corr_l, const float *corr_m, const float2 *tw, hipStream_t s);
+
 }  // namespace idg

@@ -126,3 +126,40 @@ def test_layered_major_cycle():
     err = np.abs(v[..., 0, 0] - dme).max()
     say(f"    vis vs measurement equation max {err:.2e} (w-term up to {np.abs(w * n0).max():.1f} turns)")
     assert err < 1e-4 and np.abs(v[..., 0, 3] - dme).max() < 1e-4
+
+
+def test_wstack_image_steps_four_step_sampled():
+    # N = 2048 takes the four-step transform with the layer phase fused into its sub-passes
+    require_gpu()
+    import torch
+    import paper_1909_07226_amd as idg
+    n, S2 = 2048, 1.0
+    rng = np.random.default_rng(9)
+    w0s = [-40.0, 0.0, 60.0]
+    g = (rng.standard_normal((3, 4, n, n), dtype=np.float32)
+         + 1j * rng.standard_normal((3, 4, n, n), dtype=np.float32)).astype(np.complex64)
+    cl = (0.5 + rng.random(n)).astype(np.float32)
+    cm = (0.5 + rng.random(n)).astype(np.float32)
+    xs = np.concatenate([[0, n - 1, n // 2], rng.integers(0, n, 5)])
+    ys = np.concatenate([[n - 1, 0, n // 2], rng.integers(0, n, 5)])
+    say(f"[wstack four-step] N={n} pixels {list(zip(xs.tolist(), ys.tolist()))}")
+    tl, tm = torch.from_numpy(cl).cuda(), torch.from_numpy(cm).cuda()
+    gd = torch.from_numpy(g).cuda()
+    img = torch.empty((4, n, n), dtype=torch.complex64, device="cuda")
+    idg.wstack_to_image(gd, w0s, S2, tl, tm, img)
+    idg.sync()
+    got = img[:, torch.from_numpy(ys).cuda(), torch.from_numpy(xs).cuda()].cpu().numpy()
+    ref = oim.wstack_to_image_at(g, w0s, S2, xs, ys, cl.astype(np.float64), cm.astype(np.float64))
+    scale = np.sqrt(3 * 2.0) * n / (cl.mean() * cm.mean())
+    err = np.abs(got - ref).max() / scale
+    say(f"    to image sampled err {err:.2e}")
+    assert err < 1e-4
+    im = g[1]
+    out = torch.empty((3, 4, n, n), dtype=torch.complex64, device="cuda")
+    idg.image_to_wstack(torch.from_numpy(im).cuda(), S2, tl, tm, w0s, out)
+    idg.sync()
+    got = out[:, :, torch.from_numpy(ys).cuda(), torch.from_numpy(xs).cuda()].cpu().numpy()
+    ref = oim.image_to_wstack_at(im, w0s, S2, xs, ys, cl.astype(np.float64), cm.astype(np.float64))
+    err = np.abs(got - ref).max() / (np.sqrt(2.0) * n * np.mean(1.0 / cl) * np.mean(1.0 / cm))
+    say(f"    to layers sampled err {err:.2e}")
+    assert err < 1e-4

@@ -156,3 +156,17 @@ def test_wstack_mutations_are_caught(mutation, monkeypatch):
         test_layered_major_cycle_predicts_the_measurement_equation()
     with pytest.raises(AssertionError):
         test_layered_dirty_image_matches_direct_image()
+
+
+def test_one_pixel_forms_match_the_whole_wstack():
+    rng = np.random.default_rng(12)
+    n = 32
+    g = rng.standard_normal((3, 4, n, n)) + 1j * rng.standard_normal((3, 4, n, n))
+    cl, cm = 0.5 + rng.random(n), 0.5 + rng.random(n)
+    w0s, S = [-5.0, 0.0, 7.0], 1.0
+    xs, ys = rng.integers(0, n, 6), rng.integers(0, n, 6)
+    full = oim.wstack_to_image(g, w0s, S, cl, cm)
+    assert np.allclose(oim.wstack_to_image_at(g, w0s, S, xs, ys, cl, cm), full[:, ys, xs], rtol=1e-12, atol=1e-9)
+    full = oim.image_to_wstack(g[0], w0s, S, cl, cm)
+    assert np.allclose(oim.image_to_wstack_at(g[0], w0s, S, xs, ys, cl, cm), full[:, :, ys, xs], rtol=1e-12,
+                       atol=1e-9)
