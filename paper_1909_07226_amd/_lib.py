@@ -255,7 +255,8 @@ def _common(plan, uvw_d, freqs_d, aterms_d, taper_d):
 
 
 def grid(plan, uvw_d, freqs_d, vis_d, aterms_d, taper_d, grid_d, stream=None):
-    """idg_grid: accumulate the plan's visibilities into grid_d [4, N, N] complex64."""
+    """idg_grid: accumulate the plan's visibilities into grid_d complex64, [4, N, N] (or
+    [nr_wlayers, 4, N, N] for a plan with W-layers: plan.shapes()["grid"])."""
     import torch
     sh = plan.shapes()
     u, f, a, t = _common(plan, uvw_d, freqs_d, aterms_d, taper_d)
