@@ -163,3 +163,34 @@ def test_wstack_image_steps_four_step_sampled():
     err = np.abs(got - ref).max() / (np.sqrt(2.0) * n * np.mean(1.0 / cl) * np.mean(1.0 / cm))
     say(f"    to layers sampled err {err:.2e}")
     assert err < 1e-4
+
+
+def test_layered_adjoint_at_scale():
+    # the bench's W-layer configuration: LOFAR-like geometry on a 4x wider field (S = 0.2), 20 layers,
+    # 124,673 subgrids, 10.7 GB of layer grids.  <degrid(G), y> = <G, grid(y)> holds at any size.
+    require_gpu()
+    import dataclasses
+    import torch
+    import paper_1909_07226_amd as idg
+    import synth
+    wl = synth.make_workload("lofar")
+    wl = dataclasses.replace(wl, image_size=0.2)
+    plan = idg.Plan.from_workload(wl, w_step=200.0)
+    st = plan.stats()
+    say(f"[wstack scale] {st} layers {plan.wlayers()}")
+    assert st["nr_dropped"] == 0 and plan.wlayers()[1] > 10
+    d = to_dev(wl)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    G = torch.randn(plan.shapes()["grid"], dtype=torch.complex64, device="cuda", generator=gen)
+    vis = torch.empty_like(d["vis"])
+    idg.degrid(plan, d["uvw"], d["freqs"], G, d["aterms"], d["taper"], vis)
+    gy = torch.zeros_like(G)
+    idg.grid(plan, d["uvw"], d["freqs"], d["vis"], d["aterms"], d["taper"], gy)
+    idg.sync()
+    lhs = torch.vdot(vis.flatten().to(torch.complex128), d["vis"].flatten().to(torch.complex128))
+    del vis
+    rhs = sum(torch.vdot(G[j].flatten().to(torch.complex128), gy[j].flatten().to(torch.complex128))
+              for j in range(G.shape[0]))
+    rel = float(abs(lhs - rhs) / abs(rhs))
+    say(f"    <degrid(G), y> vs <G, grid(y)>: rel {rel:.2e}")
+    assert rel < 1e-4
