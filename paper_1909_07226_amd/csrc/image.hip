@@ -232,25 +232,33 @@ __global__ void __launch_bounds__(fft_threads(N * C))
 //   step B: for each k1, the length-N2 DFT over rows k1 + N1 n2, into rows k1 + N1 k2,
 //           which is output row k = k1 + N1 k2: natural order, in place.
 // The centring signs are (-1)^n = (-1)^n2 (applied on step A's input) and
-// (-1)^k = (-1)^k1 (on step B's output).  A workgroup takes 16 adjacent columns
-// (128-byte rows) and 128 / T sub-transforms of length T: 2048 elements, 18 KiB
-// of LDS, 256 threads.  With GATHER, step A reads the element from its natural
-// row N2 n1 + n2 instead (image -> grid, whose first pass is the column transform).
+// (-1)^k = (-1)^k1 (on step B's output).  A workgroup takes 32 adjacent columns
+// (256-byte row segments, which DRAM serves better than 128-byte ones) and
+// 128 / T sub-transforms of length T: 4096 elements, 36 KiB of LDS.  With GATHER,
+// step A reads the element from its natural row N2 n1 + n2 instead (image ->
+// grid, whose first pass is the column transform).
 // SCALE 1 / 2 divide the input / output by the correction; SCALE 3 applies a
 // W-layer's exp(SIGN 2 pi i w0 n'(l, m)) (and the correction, when given) to
 // step A's input or step B's output, which then adds into `out` when acc is set.
-constexpr int kSubCols = 16, kSubElems = 128, kSubThreads = 256;
+// The plain passes run 256 threads; SCALE 3 runs 512, because its float64 phase
+// per pixel is ALU work that more waves hide better (4 workgroups per CU either way).
+constexpr int kSubCols = 32, kSubElems = 128;
+
+template <int SCALE>
+constexpr int sub_threads() {
+  return SCALE == 3 ? 512 : 256;
+}
 
 __device__ __forceinline__ int sub_lds(int i, int c) { return kSubCols * (i + (i >> 3)) + c; }
 
-template <int NTAB, int SIGN, int H, int R>
+template <int NTAB, int SIGN, int H, int R, int NT>
 __device__ __forceinline__ void sub_group(float2 *s, const float2 *__restrict__ tw, int tid) {
-  constexpr int E = 1 << R, HM = H >> (R - 1), NSET = kSubElems / E, PER = NSET * kSubCols / kSubThreads;
+  constexpr int E = 1 << R, HM = H >> (R - 1), NSET = kSubElems / E, PER = NSET * kSubCols / NT;
   constexpr int LH = ilog2c(H), LHM = ilog2c(HM);
   static_assert(PER >= 1, "work split");
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    const int w = tid + k * kSubThreads;
+    const int w = tid + k * NT;
     const int c = w % kSubCols, set = w / kSubCols;
     const int lo = set & (HM - 1), ib = lo + ((set >> LHM) << (LH + 1));
     float2 v[E];
@@ -263,15 +271,15 @@ __device__ __forceinline__ void sub_group(float2 *s, const float2 *__restrict__ 
   __syncthreads();
 }
 
-template <int NTAB, int SIGN, int H>
+template <int NTAB, int SIGN, int H, int NT>
 __device__ __forceinline__ void sub_groups(float2 *s, const float2 *__restrict__ tw, int tid) {
   if constexpr (H >= 4) {
-    sub_group<NTAB, SIGN, H, 3>(s, tw, tid);
-    sub_groups<NTAB, SIGN, H / 8>(s, tw, tid);
+    sub_group<NTAB, SIGN, H, 3, NT>(s, tw, tid);
+    sub_groups<NTAB, SIGN, H / 8, NT>(s, tw, tid);
   } else if constexpr (H == 2) {
-    sub_group<NTAB, SIGN, 2, 2>(s, tw, tid);
+    sub_group<NTAB, SIGN, 2, 2, NT>(s, tw, tid);
   } else if constexpr (H == 1) {
-    sub_group<NTAB, SIGN, 1, 1>(s, tw, tid);
+    sub_group<NTAB, SIGN, 1, 1, NT>(s, tw, tid);
   }
 }
 
@@ -288,7 +296,7 @@ __device__ __forceinline__ float2 wlayer_phasor(int x, int y, int N, double S, d
 }
 
 template <int N, bool STEP_B, bool GATHER, int SIGN, int SCALE>
-__global__ void __launch_bounds__(kSubThreads) fft_sub_kernel(const float2 *in, float2 *out,
+__global__ void __launch_bounds__(sub_threads<SCALE>()) fft_sub_kernel(const float2 *in, float2 *out,
                                                               const float2 *__restrict__ tw,
                                                               const float *__restrict__ sr,
                                                               const float *__restrict__ sc, double S, double w0,
@@ -303,18 +311,19 @@ __global__ void __launch_bounds__(kSubThreads) fft_sub_kernel(const float2 *in, 
   const int bg = blockIdx.x % NGRP, rest = blockIdx.x / NGRP;
   const int x0 = (rest % NCG) * kSubCols;
   const int64_t pbase = int64_t(rest / NCG) * N * N;
-  constexpr int PER = kSubElems * kSubCols / kSubThreads;
+  constexpr int NT = sub_threads<SCALE>(), PER = kSubElems * kSubCols / NT;
+  static_assert(PER >= 1 && NT % kSubCols == 0, "work split");
   float2 v[PER];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {  // loads first, for bytes in flight
-    const int e = tid + j * kSubThreads, c = e % kSubCols, rr = e / kSubCols;
+    const int e = tid + j * NT, c = e % kSubCols, rr = e / kSubCols;
     const int blk = bg * GB + rr / T, i = rr % T;
     const int row = STEP_B ? blk + N1 * i : (GATHER ? N2 * i + blk : N1 * blk + i);
     v[j] = in[pbase + int64_t(row) * N + x0 + c];
   }
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int e = tid + j * kSubThreads, c = e % kSubCols, rr = e / kSubCols;
+    const int e = tid + j * NT, c = e % kSubCols, rr = e / kSubCols;
     const int blk = bg * GB + rr / T, i = rr % T;
     float f = (!STEP_B && (blk & 1)) ? -1.0f : 1.0f;
     const int row = STEP_B ? blk + N1 * i : (GATHER ? N2 * i + blk : N1 * blk + i);
@@ -326,10 +335,10 @@ __global__ void __launch_bounds__(kSubThreads) fft_sub_kernel(const float2 *in, 
     s[sub_lds(rr, c)] = make_float2(v[j].x * f, v[j].y * f);
   }
   __syncthreads();
-  sub_groups<N, SIGN, T / 2>(s, tw, tid);
+  sub_groups<N, SIGN, T / 2, NT>(s, tw, tid);
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int e = tid + j * kSubThreads, c = e % kSubCols, rr = e / kSubCols;
+    const int e = tid + j * NT, c = e % kSubCols, rr = e / kSubCols;
     const int blk = bg * GB + rr / T, k = int(__brev(unsigned(rr % T)) >> (32 - lt));
     float2 x = s[sub_lds(rr, c)];
     int row;
@@ -363,7 +372,7 @@ static hipError_t launch_fft_sub(const float2 *in, float2 *out, const float2 *tw
                                  hipStream_t st, double S = 0.0, double w0 = 0.0, bool acc = false) {
   constexpr int N1 = four_step_n1<N>(), N2 = N / N1, T = STEP_B ? N2 : N1, NBLK = STEP_B ? N1 : N2;
   constexpr int64_t blocks = int64_t(4) * (N / kSubCols) * (NBLK / (kSubElems / T));
-  hipLaunchKernelGGL((fft_sub_kernel<N, STEP_B, GATHER, SIGN, SCALE>), dim3(unsigned(blocks)), dim3(kSubThreads), 0,
+  hipLaunchKernelGGL((fft_sub_kernel<N, STEP_B, GATHER, SIGN, SCALE>), dim3(unsigned(blocks)), dim3(sub_threads<SCALE>()), 0,
                      st, in, out, tw, sr, sc, S, w0, int(acc));
   return hipGetLastError();
 }
@@ -458,7 +467,7 @@ static hipError_t launch_fft_batch(const float2 *in, float2 *out, const float2 *
 // LDS would read fewer than 16 columns (128 bytes) per row.
 template <int N>
 constexpr bool use_four_step() {
-  return col_batch<N>() < kSubCols && N >= 2048;
+  return col_batch<N>() < 16 && N >= 2048;
 }
 
 #define IDG_DISPATCH_N(N, ...)                                    \
