@@ -5,7 +5,7 @@
 * the workload grid sizes (512, 4096, 8192): sampled pixels / cells that the
   oracle computes one by one, plus the round trip image_to_grid(grid_to_image(g))
   = N^2 g, which holds at any size;
-* the largest size (16384): the round trip;
+* the largest size (16384): sampled pixels of two planes and the round trip;
 * the adjoint identity on the GPU's outputs;
 * the major cycle: model image -> grid -> degrid against the oracle's chain and
   against the measurement equation of a point source.
@@ -134,13 +134,41 @@ def test_workload_sizes_sampled_and_round_trip(N):
     assert rel < GRID_RMS_TOL
 
 
-def test_largest_size_round_trip():
+def test_largest_size_sampled_and_round_trip():
+    # N = 16384: sampled pixels of planes 0 and 3 (plane 3 starts 6 GiB into the array) against the
+    # oracle in both directions, then the round trip
     require_gpu()
     import torch
+    import paper_1909_07226_amd as idg
     N = 16384
-    say(f"[image round trip] N={N}")
+    rng = np.random.default_rng(16384)
+    cl, cm = _corr(rng, N)
+    xs = np.concatenate([[0, N - 1, N // 2], rng.integers(0, N, 2)])
+    ys = np.concatenate([[N - 1, 0, N // 2], rng.integers(0, N, 2)])
+    planes = [0, 3]
+    say(f"[image sampled] N={N} planes {planes} pixels {list(zip(xs.tolist(), ys.tolist()))}")
     gen = torch.Generator(device="cuda").manual_seed(11)
     gd = torch.randn((4, N, N), dtype=torch.complex64, device="cuda", generator=gen)
+    g = np.stack([gd[p].cpu().numpy() for p in planes])
+    rms_in = float(np.sqrt(np.mean(np.abs(g[0]) ** 2)))
+    tl, tm = torch.from_numpy(cl).cuda(), torch.from_numpy(cm).cuda()
+    sy, sx = torch.from_numpy(ys).cuda(), torch.from_numpy(xs).cuda()
+    out = torch.empty_like(gd)
+    idg.grid_to_image(gd, tl, tm, out)
+    idg.sync()
+    got = np.stack([out[p, sy, sx].cpu().numpy() for p in planes])
+    ref = oim.grid_to_image_at(g, xs, ys, cl.astype(np.float64), cm.astype(np.float64))
+    err = np.abs(got - ref).max() / (rms_in * N)
+    say(f"    grid->image sampled err {err:.2e}")
+    assert err < IMAGE_MAX_TOL
+    idg.image_to_grid(gd, tl, tm, out)
+    idg.sync()
+    got = np.stack([out[p, sy, sx].cpu().numpy() for p in planes])
+    ref = oim.image_to_grid_at(g, xs, ys, cl.astype(np.float64), cm.astype(np.float64))
+    err = np.abs(got - ref).max() / (rms_in * N * np.abs(1.0 / cl).mean() * np.abs(1.0 / cm).mean())
+    say(f"    image->grid sampled err {err:.2e}")
+    assert err < IMAGE_MAX_TOL
+    del out, g
     rel = _round_trip_rel(gd)
     say(f"    round trip rel {rel:.2e}")
     assert rel < GRID_RMS_TOL
