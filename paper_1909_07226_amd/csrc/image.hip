@@ -240,8 +240,9 @@ __global__ void __launch_bounds__(fft_threads(N * C))
 // SCALE 1 / 2 divide the input / output by the correction; SCALE 3 applies a
 // W-layer's exp(SIGN 2 pi i w0 n'(l, m)) (and the correction, when given) to
 // step A's input or step B's output, which then adds into `out` when acc is set.
-// The plain passes run 256 threads; SCALE 3 runs 512, because its float64 phase
-// per pixel is ALU work that more waves hide better (4 workgroups per CU either way).
+// The plain passes run 256 threads; SCALE 3 runs 512, because its per-pixel phase
+// (float64 square root and range reduction) is ALU work that more waves hide
+// better (4 workgroups per CU either way).
 constexpr int kSubCols = 32, kSubElems = 128;
 
 template <int SCALE>
@@ -298,11 +299,9 @@ __device__ __forceinline__ float2 wlayer_phasor(int x, int y, int N, double S, d
 }
 
 template <int N, bool STEP_B, bool GATHER, int SIGN, int SCALE>
-__global__ void __launch_bounds__(sub_threads<SCALE>()) fft_sub_kernel(const float2 *in, float2 *out,
-                                                              const float2 *__restrict__ tw,
-                                                              const float *__restrict__ sr,
-                                                              const float *__restrict__ sc, double S, double w0,
-                                                              int acc) {
+__global__ void __launch_bounds__(sub_threads<SCALE>())
+    fft_sub_kernel(const float2 *in, float2 *out, const float2 *__restrict__ tw, const float *__restrict__ sr,
+                   const float *__restrict__ sc, double S, double w0, int acc) {
   constexpr int N1 = four_step_n1<N>(), N2 = N / N1;
   constexpr int T = STEP_B ? N2 : N1, GB = kSubElems / T, NBLK = STEP_B ? N1 : N2;
   constexpr int NGRP = NBLK / GB, NCG = N / kSubCols;
@@ -374,8 +373,8 @@ static hipError_t launch_fft_sub(const float2 *in, float2 *out, const float2 *tw
                                  hipStream_t st, double S = 0.0, double w0 = 0.0, bool acc = false) {
   constexpr int N1 = four_step_n1<N>(), N2 = N / N1, T = STEP_B ? N2 : N1, NBLK = STEP_B ? N1 : N2;
   constexpr int64_t blocks = int64_t(4) * (N / kSubCols) * (NBLK / (kSubElems / T));
-  hipLaunchKernelGGL((fft_sub_kernel<N, STEP_B, GATHER, SIGN, SCALE>), dim3(unsigned(blocks)), dim3(sub_threads<SCALE>()), 0,
-                     st, in, out, tw, sr, sc, S, w0, int(acc));
+  hipLaunchKernelGGL((fft_sub_kernel<N, STEP_B, GATHER, SIGN, SCALE>), dim3(unsigned(blocks)),
+                     dim3(sub_threads<SCALE>()), 0, st, in, out, tw, sr, sc, S, w0, int(acc));
   return hipGetLastError();
 }
 
