@@ -128,21 +128,22 @@ def test_layered_major_cycle():
     assert err < 1e-4 and np.abs(v[..., 0, 3] - dme).max() < 1e-4
 
 
-def test_wstack_image_steps_four_step_sampled():
-    # N = 2048 takes the four-step transform with the layer phase fused into its sub-passes
+@pytest.mark.parametrize("w0s", [[-40.0, 0.0, 60.0], [-3000.0, 25.0, 4500.0]])
+def test_wstack_image_steps_four_step_sampled(w0s):
+    # N = 2048 takes the four-step transform with the layer phase fused into its sub-passes; the
+    # second set puts up to ~1300 turns of w-term at the field edge (the phase is reduced in float64)
     require_gpu()
     import torch
     import paper_1909_07226_amd as idg
     n, S2 = 2048, 1.0
     rng = np.random.default_rng(9)
-    w0s = [-40.0, 0.0, 60.0]
     g = (rng.standard_normal((3, 4, n, n), dtype=np.float32)
          + 1j * rng.standard_normal((3, 4, n, n), dtype=np.float32)).astype(np.complex64)
     cl = (0.5 + rng.random(n)).astype(np.float32)
     cm = (0.5 + rng.random(n)).astype(np.float32)
     xs = np.concatenate([[0, n - 1, n // 2], rng.integers(0, n, 5)])
     ys = np.concatenate([[n - 1, 0, n // 2], rng.integers(0, n, 5)])
-    say(f"[wstack four-step] N={n} pixels {list(zip(xs.tolist(), ys.tolist()))}")
+    say(f"[wstack four-step] N={n} w0s {w0s} pixels {list(zip(xs.tolist(), ys.tolist()))}")
     tl, tm = torch.from_numpy(cl).cuda(), torch.from_numpy(cm).cuda()
     gd = torch.from_numpy(g).cuda()
     img = torch.empty((4, n, n), dtype=torch.complex64, device="cuda")
