@@ -7,19 +7,30 @@ the whole hot path (plan reused, as in every major cycle of an imager).
 Inputs are resident in HBM before the timed region.  Prints one JSON line:
 value = planned visibilities / (wall time of grid + degrid), in MVis/s.
 
-    python bench.py [--steps K] [--warmup W] [--workload lofar|tiny|skalow]
+    python bench.py [--steps K] [--warmup W] [--workload skalow|lofar|tiny]
 
-The roofline entry is for the gridder kernel: algorithmic work 34 flop per
-(visibility, subgrid pixel) -- one phase multiply-add and 16 multiply-adds of
-the 4-polarisation complex accumulate; sin and cos are not counted -- divided
-by the gridder's average launch time from HIP events recorded by the library
-on the launching stream.  The CPU baseline is the float64 oracle on a bounded
-sample, timed on this host.
+The headline workload is the SKA-low-like single-GPU share (the largest
+configuration that fits one GPU); the LOFAR-like workload runs as a second
+leg (key "lofar"), with the W-layer and serving legs on its geometry.
+
+Roofline: the gridder and the degridder are bound by the FP32 VALU.  Their
+algorithmic work per launch is counted as
+  34 flop per (visibility, subgrid pixel): one phase multiply-add and 16
+     multiply-adds of the 4-polarisation complex accumulate (sin and cos not
+     counted);
+  136 flop per pixel per subgrid: the two 2 x 2 complex Jones products and the
+     taper;
+  5 L^2 log2(L^2) flop per polarisation per subgrid: the subgrid transform,
+and divided by the kernel's average launch time from HIP events recorded by
+the library on the launching stream.  "roofline" is for the dominant (longer)
+of the two kernels; both are reported.  The CPU baseline is the float64 oracle
+on a bounded sample, timed on this host.
 """
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -28,19 +39,23 @@ import time
 import numpy as np
 
 FLOP_PER_VIS_PIX = 34
-FP32_PEAK_TFLOPS = 157.3           # MI355X FP32 vector peak (256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 x 2.4 GHz)
+FLOP_PER_PIX_ATERM = 136
+# MI355X FP32 vector peak: 256 CUs x 2 wave64 FMA instructions per CU-cycle x 64 lanes x 2 flop x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0               # MI355X HBM3E
 WORKLOAD_DESC = {
+    "skalow": "skalow-like share: 512 stations (130816 baselines), 64 x 1 s, 16 ch 50-350 MHz, L=32, "
+              "8192^2 grid at 1 arcsec, A-terms every 32 timesteps, 10% flags",
     "lofar": "lofar-like: 48 stations (1128 baselines), 2048 x 1 s, 16 ch 120-180 MHz, |w| <= 2e3 lambda, "
              "L=32 subgrids of <=128 timesteps, 4096^2 grid at 2.5 arcsec, near-identity A-terms every 256 s",
     "tiny": "tiny: 8 stations (28 baselines), 32 x 10 s, 4 ch 150-151 MHz, w=0, L=24, 512^2 grid at 1 arcmin",
-    "skalow": "skalow-like share: 512 stations (130816 baselines), 64 x 1 s, 16 ch 50-350 MHz, L=32, "
-              "8192^2 grid at 1 arcsec, A-terms every 32 timesteps, 10% flags",
 }
-
+# baseline stride of the oracle's bounded sample (cpu_baseline)
+CPU_SAMPLE_STRIDE = {"skalow": 256, "lofar": 16, "tiny": 1}
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1909_07226_amd", "csrc", "kernels.hip")
-HBM_RECORD = os.path.join(ROOT, "profiles", "lofar_hbm_counters.md")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_hash():
@@ -48,31 +63,77 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def gridder_traffic(workload, form):
-    """HBM bytes per gridder launch from the committed counter summary.
+def algorithmic_flops(nvis, nsub, L):
+    """Flops of one direction (gridder or degridder) over nvis visibilities in nsub subgrids of L x L."""
+    npix = L * L
+    return (FLOP_PER_VIS_PIX * float(nvis) * npix + FLOP_PER_PIX_ATERM * float(npix) * nsub
+            + 5.0 * npix * math.log2(npix) * 4 * nsub)
 
-    The summary's ``traffic-record:`` line holds FETCH_SIZE and WRITE_SIZE (KiB
-    per dispatch) of the gridder and the factors that map each counter onto
-    the bytes of a plain elementwise kernel of known size.  Returns None when
-    there is no record for this workload and schedule, or when the kernel
-    source has changed since the counters were taken.
+
+def hbm_record_path(workload):
+    return os.path.join(PROFILES, f"{workload}_hbm_counters.md")
+
+
+def kernel_traffic(workload, kernel, schedule, path=None):
+    """HBM bytes per launch of `kernel` ("gridder" / "degridder") from the committed counter summary.
+
+    The summary's ``traffic-record:`` lines hold FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch) of one kernel and the factors that map each counter onto the
+    bytes of a plain elementwise kernel of known size.  ``schedule`` is the
+    tuning string the counters were taken with.  Returns None when there is no
+    record for this workload, kernel and schedule, or when the kernel source
+    has changed since the counters were taken.
     """
     try:
-        with open(HBM_RECORD) as f:
-            m = re.search(r"^traffic-record: (.*)$", f.read(), re.M)
+        with open(path or hbm_record_path(workload)) as f:
+            text = f.read()
     except OSError:
         return None
-    if not m:
-        return None
-    rec = dict(kv.split("=", 1) for kv in m.group(1).split())
-    if rec.get("workload") != workload or rec.get("form") != form or rec.get("kernels_sha256") != kernel_source_hash():
-        return None
-    return int(round(float(rec["fetch_kib"]) * 1024 * float(rec["fetch_factor"])
-                     + float(rec["write_kib"]) * 1024 * float(rec["write_factor"])))
+    for m in re.finditer(r"^traffic-record: (.*)$", text, re.M):
+        rec = dict(kv.split("=", 1) for kv in m.group(1).split())
+        if (rec.get("workload") == workload and rec.get("kernel") == kernel and rec.get("schedule") == schedule
+                and rec.get("kernels_sha256") == kernel_source_hash()):
+            return int(round(float(rec["fetch_kib"]) * 1024 * float(rec["fetch_factor"])
+                             + float(rec["write_kib"]) * 1024 * float(rec["write_factor"])))
+    return None
+
+
+def schedule_string(tuning, kernel):
+    """The part of a plan's tuning that selects `kernel`'s launch shape."""
+    if kernel == "gridder":
+        return f"{tuning['grid_form']}/{tuning['grid_blocks_per_cu']}"
+    return f"{tuning['degrid_form']}/{tuning['degrid_blocks_per_cu']}/{tuning['degrid_shape']}"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline (the float64 oracle on a bounded sample of the same workload)
+
+
+def host_cores():
+    """(cores this process may run on, CPU model, cgroup CPU quota in cores or None)."""
+    aff = len(os.sched_getaffinity(0))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, period = f.read().split()[:2]
+            if q != "max":
+                quota = float(q) / float(period)
+    except (OSError, ValueError):
+        pass
+    return aff, model, quota
 
 
 def _oracle_worker(args):
@@ -91,42 +152,49 @@ def _oracle_worker(args):
 _G = {}
 
 
-def cpu_baseline(wl, budget_s):
-    """Time the oracle (as it stands) on every 16th baseline's subgrids, within ~budget_s seconds."""
+def cpu_baseline(wl, budget_s, max_procs):
+    """Time the oracle (as it stands) on a baseline subset's subgrids, within ~budget_s seconds."""
     import multiprocessing as mp
     import synth
     from oracle.plan import F, plan_workload
-    cores = max(1, min(16, len(os.sched_getaffinity(0))))
-    sub_wl = synth.subset(wl, baselines=np.arange(0, wl.nr_baselines, 16))
+    aff, model, quota = host_cores()
+    cores = aff if quota is None else max(1, min(aff, int(quota)))
+    procs = max(1, min(cores, max_procs))
+    stride = CPU_SAMPLE_STRIDE.get(wl.name, 16)
+    sub_wl = synth.subset(wl, baselines=np.arange(0, wl.nr_baselines, stride))
     oplan = plan_workload(sub_wl)
     nvis = oplan.subgrids[:, F["nvis"]]
     # calibrate on a few subgrids, then pick a prefix of the subgrid list that fits the budget
     _G.update(plan=oplan, uvw=sub_wl.uvw, freqs=sub_wl.freqs, vis=sub_wl.vis, aterms=sub_wl.aterms,
               taper=sub_wl.taper, grid=np.zeros((4, wl.grid_size, wl.grid_size), np.complex64))
     t = time.perf_counter()
-    for p in range(min(4, oplan.nr_subgrids)):
+    ncal = min(8, oplan.nr_subgrids)
+    for p in range(ncal):
         _oracle_worker((p, "grid"))
         _oracle_worker((p, "degrid"))
-    per_vis = (time.perf_counter() - t) / max(1, int(nvis[:4].sum()))
-    target = budget_s * cores / per_vis
+    per_vis = (time.perf_counter() - t) / max(1, int(nvis[:ncal].sum()))
+    target = budget_s * procs / per_vis
     n = int(np.searchsorted(np.cumsum(nvis), target)) + 1
     n = max(1, min(n, oplan.nr_subgrids))
     ids = list(range(n))
     ctx = mp.get_context("fork")
-    with ctx.Pool(cores) as pool:
+    with ctx.Pool(procs) as pool:
         t0 = time.perf_counter()
         pool.map(_oracle_worker, [(p, "grid") for p in ids], chunksize=4)
         t1 = time.perf_counter()
         pool.map(_oracle_worker, [(p, "degrid") for p in ids], chunksize=4)
         t2 = time.perf_counter()
     k = int(nvis[:n].sum())
-    return {"value": round(k / (t2 - t0) / 1e6, 6), "unit": "MVis/s", "cores": cores, "kind": "oracle",
+    return {"value": round(k / (t2 - t0) / 1e6, 6), "unit": "MVis/s", "cores": procs, "kind": "oracle",
             "sample": f"float64 numpy oracle, grid then degrid of the first {n} of {oplan.nr_subgrids} subgrids "
-                      f"of every 16th baseline ({k} visibilities), {cores} processes",
+                      f"of every {stride}th baseline of the {wl.name} workload ({k} visibilities), "
+                      f"{procs} worker processes",
+            "cpu_model": model, "affinity_cores": aff, "cgroup_quota_cores": quota,
             "grid_s": round(t1 - t0, 3), "degrid_s": round(t2 - t1, 3)}
 
 
-HBM_PEAK_GBS = 8000.0               # MI355X HBM3E
+# ---------------------------------------------------------------------------
+# HBM-bound stages
 
 
 def touched_tile_count(plan, tile=32):
@@ -145,6 +213,12 @@ def touched_tile_count(plan, tile=32):
             ok = (tx <= (x0 + L - 1) // tile) & (ty <= (y0 + L - 1) // tile)
             ids.append((ty * ntx + tx)[ok])
     return int(np.unique(np.concatenate(ids)).size)
+
+
+# passes over the [4][N][N] array of the master grid <-> image steps: one row pass, then one column
+# pass (N <= 1024) or the two sub-passes of the four-step column transform (N >= 2048)
+def image_passes(N):
+    return 2 if N <= 1024 else 3
 
 
 def hbm_stages(idg, torch, plan, grid, stream, adder_ms_per_step, log, max_subgrids=65536, reps=5):
@@ -180,18 +254,19 @@ def hbm_stages(idg, torch, plan, grid, stream, adder_ms_per_step, log, max_subgr
     out["splitter"] = dict(ms=round(t, 4), bytes=2 * n * sub_bytes, subgrids=n)
     t = timed(lambda: idg.subgrid_fft(buf, -1, stream))
     out["subgrid_fft"] = dict(ms=round(t, 4), bytes=2 * n * sub_bytes, subgrids=n)
-    # master grid <-> image (four passes over the [4, N, N] array: rows, transpose, rows, transpose);
-    # algorithmic bytes are one read of the input and one write of the output
+    # master grid <-> image; algorithmic bytes are one read of the input and one write of the output,
+    # and every pass reads and writes the array once
     N = grid.shape[-1]
     corr = torch.ones(N, dtype=torch.float32, device="cuda")
     img = torch.empty_like(grid)
     arr = 4 * N * N * 8
+    npass = image_passes(N)
     t = timed(lambda: idg.grid_to_image(grid, corr, corr, img, stream))
-    out["grid_to_image"] = dict(ms=round(t, 4), bytes=2 * arr, grid_size=N, passes=4,
-                                pass_gb_s=round(8 * arr / (t * 1e-3) / 1e9, 1))
+    out["grid_to_image"] = dict(ms=round(t, 4), bytes=2 * arr, grid_size=N, passes=npass,
+                                pass_gb_s=round(2 * npass * arr / (t * 1e-3) / 1e9, 1))
     t = timed(lambda: idg.image_to_grid(img, corr, corr, grid, stream))
-    out["image_to_grid"] = dict(ms=round(t, 4), bytes=2 * arr, grid_size=N, passes=4,
-                                pass_gb_s=round(8 * arr / (t * 1e-3) / 1e9, 1))
+    out["image_to_grid"] = dict(ms=round(t, 4), bytes=2 * arr, grid_size=N, passes=npass,
+                                pass_gb_s=round(2 * npass * arr / (t * 1e-3) / 1e9, 1))
     del img
     tiles = touched_tile_count(plan)
     out["adder"] = dict(ms=round(adder_ms_per_step, 4), bytes=P * sub_bytes + 2 * tiles * 4 * 32 * 32 * 8,
@@ -203,6 +278,10 @@ def hbm_stages(idg, torch, plan, grid, stream, adder_ms_per_step, log, max_subgr
         log(f"[bench] {k}: {v['bytes'] / 1e9:.3f} GB in {v['ms']:.3f} ms = {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.1%})")
     del buf
     return out
+
+
+# ---------------------------------------------------------------------------
+# legs on the LOFAR-like geometry: serving and W-layers
 
 
 def serving_leg(lofar_wl, lofar_dev, n_jobs, log):
@@ -302,13 +381,184 @@ def wstack_leg(idg, torch, wl, tuned, log, image_size=0.2, w_step=200.0, steps=3
     return out
 
 
+# ---------------------------------------------------------------------------
+# one workload: plan, schedule, timed steps
+
+
+class Leg:
+    """Plan and device inputs of one workload, and the timed grid + degrid step."""
+
+    def __init__(self, idg, torch, name, args, log):
+        import synth
+        self.idg, self.torch, self.name, self.log = idg, torch, name, log
+        log(f"[bench] building workload {name}")
+        t = time.perf_counter()
+        wl = synth.make_workload(name)
+        log(f"[bench] workload built in {time.perf_counter() - t:.1f} s")
+        t = time.perf_counter()
+        plan = idg.Plan.from_workload(wl)
+        self.plan_ms = (time.perf_counter() - t) * 1e3
+        nsub = plan.stats()["nr_subgrids"]
+        scratch = (int(args.scratch_gb * 1e9) if args.scratch_gb > 0
+                   else nsub * 4 * wl.subgrid_size ** 2 * 8 + (1 << 20))
+        if scratch != 2 << 30:
+            # the scratch budget is a plan parameter: re-plan with it (planning time is the first plan's)
+            plan = idg.Plan.from_workload(wl, scratch_bytes=scratch)
+        self.wl, self.plan, self.scratch = wl, plan, scratch
+        self.st = plan.stats()
+        log(f"[bench] plan: {self.st} in {self.plan_ms:.0f} ms")
+        dev = "cuda"
+        self.uvw = torch.from_numpy(wl.uvw).to(dev)
+        self.freqs = torch.from_numpy(wl.freqs).to(dev)
+        self.vis = torch.from_numpy(wl.vis).to(dev)
+        self.aterms = torch.from_numpy(wl.aterms).to(dev)
+        self.taper = torch.from_numpy(wl.taper).to(dev)
+        N = wl.grid_size
+        self.grid = torch.zeros((4, N, N), dtype=torch.complex64, device=dev)
+        self.vis_out = torch.empty_like(self.vis)
+        self.stream = torch.cuda.current_stream()
+
+    def dev_inputs(self):
+        return dict(uvw=self.uvw, freqs=self.freqs, vis=self.vis, aterms=self.aterms, taper=self.taper)
+
+    def step(self):
+        idg = self.idg
+        self.grid.zero_()
+        idg.grid(self.plan, self.uvw, self.freqs, self.vis, self.aterms, self.taper, self.grid, self.stream)
+        idg.degrid(self.plan, self.uvw, self.freqs, self.grid, self.aterms, self.taper, self.vis_out, self.stream)
+
+    def timed(self, steps, warmup):
+        """(ms per step from the host clock, stage profile, per-step HIP-event distribution)."""
+        idg, torch = self.idg, self.torch
+        for _ in range(warmup):
+            self.step()
+        idg.sync(self.stream)
+        torch.cuda.synchronize()
+        idg.profile(True)
+        idg.profile_read(reset=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        t0 = time.perf_counter()
+        ev[0].record(self.stream)
+        for i in range(steps):
+            self.step()
+            ev[i + 1].record(self.stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        idg.sync(self.stream)
+        prof = idg.profile_read(reset=True)
+        idg.profile(False)
+        per_step = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+        dist = dict(median=round(float(np.median(per_step)), 4), p90=round(float(np.percentile(per_step, 90)), 4),
+                    min=round(float(per_step.min()), 4), max=round(float(per_step.max()), 4))
+        return (t1 - t0) * 1e3 / steps, prof, dist
+
+    def schedule(self, args):
+        """Set the plan's schedule: autotuned (args.form == "auto") or as given.  Returns autotune info."""
+        plan = self.plan
+        tune_info = None
+        if args.form == "auto":
+            from paper_1909_07226_amd.autotune import autotune
+            self.log(f"[bench] {self.name}: autotuning the schedule (outside the timed region)")
+            tune_info = autotune(plan, self.uvw, self.freqs, self.vis, self.aterms, self.taper, self.grid,
+                                 self.vis_out, use_cache=False, log=self.log)
+        else:
+            plan.set_tuning(form=args.form, blocks_per_cu=args.blocks_per_cu, degrid_shape=args.degrid_shape)
+        if args.adder_chunk:
+            plan.set_tuning(adder_chunk=args.adder_chunk)
+        return tune_info
+
+    def measure(self, args, steps, warmup):
+        """Timed steps under the current schedule, with per-kernel rooflines."""
+        ms_step, prof, dist = self.timed(steps, warmup)
+        nvis, nsub = self.st["nr_gridded"], self.st["nr_subgrids"]
+        L = self.wl.subgrid_size
+        k = steps
+        flops_step = algorithmic_flops(nvis, nsub, L)
+        tuned = self.plan.get_tuning()
+        kernels = {}
+        for kern in ("gridder", "degridder"):
+            ms, n = prof[kern]
+            launch_ms = ms / max(1, n)
+            per_step_launches = max(1, n // k)
+            achieved = (flops_step / per_step_launches) / (launch_ms * 1e-3) / 1e12
+            kernels[kern] = {"bound": "alu", "kernel": kern, "achieved": round(achieved, 3),
+                             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                             "traffic": kernel_traffic(self.name, kern, schedule_string(tuned, kern)),
+                             "traffic_unit": "bytes/launch", "schedule": schedule_string(tuned, kern),
+                             "kernels_sha256": kernel_source_hash(),
+                             "flop_per_launch": flops_step / per_step_launches,
+                             "work_per_launch": f"({FLOP_PER_VIS_PIX} flop x {nvis} vis + "
+                                                f"{FLOP_PER_PIX_ATERM} flop x {nsub} subgrids) x {L * L} pix + "
+                                                f"5 L^2 log2(L^2) x 4 pol x {nsub} subgrids"
+                                                + (f", over {per_step_launches} launches" if per_step_launches > 1
+                                                   else ""),
+                             "avg_launch_ms": round(launch_ms, 4), "launches_per_step": per_step_launches}
+        a_ms, _ = prof["adder"]
+        z_ms, _ = prof["zero"]
+        g_ms = (prof["gridder"][0] + a_ms) / k
+        d_ms = (prof["degridder"][0] + z_ms) / k
+        dominant = max(("gridder", "degridder"), key=lambda kk: prof[kk][0])
+        out = {"value": round(nvis / (ms_step * 1e-3) / 1e6, 3), "ms_per_step": round(ms_step, 4), "step_ms": dist,
+               "grid_mvis_s": round(nvis / (g_ms * 1e-3) / 1e6, 3),
+               "degrid_mvis_s": round(nvis / (d_ms * 1e-3) / 1e6, 3),
+               "kernels_ms_per_step": {kk: round(prof[kk][0] / k, 4) for kk in ("gridder", "adder", "degridder",
+                                                                                 "zero")},
+               "roofline": kernels[dominant], "gridder_roofline": kernels["gridder"],
+               "degridder_roofline": kernels["degridder"], "tuning": tuned}
+        self.log(f"[bench] {self.name}: {ms_step:.2f} ms/step, {out['value']:.1f} MVis/s; "
+                 f"gridder {kernels['gridder']['avg_launch_ms']:.3f} ms/launch ({kernels['gridder']['frac']:.1%}), "
+                 f"adder {a_ms / k:.3f} ms, degridder {kernels['degridder']['avg_launch_ms']:.3f} ms/launch "
+                 f"({kernels['degridder']['frac']:.1%})")
+        return out
+
+    def config(self):
+        wl = self.wl
+        return {"workload": WORKLOAD_DESC[self.name], "nr_visibilities": self.st["nr_gridded"],
+                "nr_subgrids": self.st["nr_subgrids"], "subgrid_size": wl.subgrid_size, "grid_size": wl.grid_size,
+                "polarisations": 4, "phase_offsets": "f64", "taper": "PSWF beta=7", "scratch_bytes": self.scratch,
+                "tuning": self.plan.get_tuning()}
+
+    def release(self):
+        for k in ("uvw", "freqs", "vis", "aterms", "taper", "grid", "vis_out"):
+            setattr(self, k, None)
+        self.torch.cuda.empty_cache()
+
+
+def run_leg(idg, torch, name, args, log, compare_plain=True):
+    leg = Leg(idg, torch, name, args, log)
+    tune_info = leg.schedule(args)
+    log(f"[bench] {name}: tuning {leg.plan.get_tuning()}; warmup {args.warmup}, timing {args.steps} steps")
+    res = leg.measure(args, args.steps, args.warmup)
+    res["plan_ms"] = round(leg.plan_ms, 1)
+    res["autotune_ms"] = tune_info["timings_ms"] if tune_info else None
+    res["plain_form"] = None
+    if compare_plain and args.form == "auto":
+        tuned = leg.plan.get_tuning()
+        # the plain form with the same degridder shape and adder chunk: only the launch form differs
+        leg.plan.set_tuning(form="plain", blocks_per_cu=0, adder_chunk=tuned["adder_chunk"],
+                            degrid_shape=tuned["degrid_shape"])
+        p_ms, prof, dist = leg.timed(args.steps, 1)
+        k = args.steps
+        res["plain_form"] = {"ms_per_step": round(p_ms, 4),
+                             "value": round(leg.st["nr_gridded"] / (p_ms * 1e-3) / 1e6, 3), "step_ms": dist,
+                             "degrid_shape": tuned["degrid_shape"],
+                             "kernels_ms_per_step": {kk: round(prof[kk][0] / k, 4) for kk in ("gridder", "adder",
+                                                                                              "degridder")}}
+        log(f"[bench] {name}: plain form {res['plain_form']}")
+        leg.plan.set_tuning(**tuned)
+    return leg, res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="lofar", choices=sorted(WORKLOAD_DESC))
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="skalow", choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="most worker processes for the CPU baseline (the host's CPU share of one GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--form", default="auto", choices=("auto", "plain", "persistent"),
                     help="gridder/degridder schedule: autotuned (default), one workgroup per subgrid, or a "
@@ -317,8 +567,11 @@ def main():
     ap.add_argument("--degrid-shape", default="standard", choices=("standard", "wide"),
                     help="degridder task shape when --form is given (autotuned otherwise)")
     ap.add_argument("--adder-chunk", type=int, default=0, help="adder: longest tile-list run per workgroup (0 = 256)")
+    ap.add_argument("--no-lofar", action="store_true",
+                    help="skip the LOFAR-like leg (and the W-layer and serving legs on its geometry)")
     ap.add_argument("--serve-jobs", type=int, default=400, help="jobs in the serving trace (0 = skip serving)")
     ap.add_argument("--no-wstack", action="store_true", help="skip the W-layer leg (wider field, layered plan)")
+    ap.add_argument("--no-hbm-stages", action="store_true", help="skip the standalone HBM-bound stage timings")
     ap.add_argument("--scratch-gb", type=float, default=0.0,
                     help="subgrid scratch budget in GB (0 = enough for the whole plan: one gridder launch)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -331,148 +584,54 @@ def main():
 
     import torch
     import paper_1909_07226_amd as idg
-    import synth
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a HIP device")
     idg.lib()
 
-    log(f"[bench] building workload {args.workload}")
-    wl = synth.make_workload(args.workload)
-    t = time.perf_counter()
-    plan = idg.Plan.from_workload(wl)
-    plan_ms = (time.perf_counter() - t) * 1e3
-    nsub = plan.stats()["nr_subgrids"]
-    scratch = int(args.scratch_gb * 1e9) if args.scratch_gb > 0 else nsub * 4 * wl.subgrid_size ** 2 * 8 + (1 << 20)
-    if scratch != 2 << 30:
-        # the scratch budget is a plan parameter: re-plan with it (planning time is the first plan's)
-        plan = idg.Plan.from_workload(wl, scratch_bytes=scratch)
-    st = plan.stats()
-    nvis = st["nr_gridded"]
-    L, N = wl.subgrid_size, wl.grid_size
-    log(f"[bench] plan: {st} in {plan_ms:.0f} ms")
-    dev = "cuda"
-    uvw = torch.from_numpy(wl.uvw).to(dev)
-    freqs = torch.from_numpy(wl.freqs).to(dev)
-    vis = torch.from_numpy(wl.vis).to(dev)
-    aterms = torch.from_numpy(wl.aterms).to(dev)
-    taper = torch.from_numpy(wl.taper).to(dev)
-    grid = torch.zeros((4, N, N), dtype=torch.complex64, device=dev)
-    vis_out = torch.empty_like(vis)
-    stream = torch.cuda.current_stream()
-
-    def step():
-        grid.zero_()
-        idg.grid(plan, uvw, freqs, vis, aterms, taper, grid, stream)
-        idg.degrid(plan, uvw, freqs, grid, aterms, taper, vis_out, stream)
-
-    def timed(steps, warmup):
-        for _ in range(warmup):
-            step()
-        idg.sync(stream)
-        torch.cuda.synchronize()
-        idg.profile(True)
-        idg.profile_read(reset=True)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-        t0 = time.perf_counter()
-        ev[0].record(stream)
-        for i in range(steps):
-            step()
-            ev[i + 1].record(stream)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        idg.sync(stream)
-        prof = idg.profile_read(reset=True)
-        idg.profile(False)
-        per_step = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
-        timed.dist = dict(median=round(float(np.median(per_step)), 4),
-                          p90=round(float(np.percentile(per_step, 90)), 4),
-                          min=round(float(per_step.min()), 4), max=round(float(per_step.max()), 4))
-        return (t1 - t0) * 1e3 / steps, prof
-
-    tune_info = None
-    if args.form == "auto":
-        from paper_1909_07226_amd.autotune import autotune
-        log("[bench] autotuning the schedule (outside the timed region)")
-        tune_info = autotune(plan, uvw, freqs, vis, aterms, taper, grid, vis_out, use_cache=False, log=log)
-    else:
-        plan.set_tuning(form=args.form, blocks_per_cu=args.blocks_per_cu, degrid_shape=args.degrid_shape)
-    if args.adder_chunk:
-        plan.set_tuning(adder_chunk=args.adder_chunk)
-    log(f"[bench] tuning {plan.get_tuning()}; warmup {args.warmup}, timing {args.steps} steps")
-    ms_step, prof = timed(args.steps, args.warmup)
-    step_dist = dict(timed.dist)
-    value = nvis / (ms_step * 1e-3) / 1e6
-    k = args.steps
-    g_ms, g_n = prof["gridder"]
-    a_ms, a_n = prof["adder"]
-    d_ms, d_n = prof["degridder"]
-    z_ms, z_n = prof["zero"]
-    grid_ms = (g_ms + a_ms) / k
-    degrid_ms = (d_ms + z_ms) / k
-    flops_step = FLOP_PER_VIS_PIX * float(nvis) * L * L
-    g_launch_ms = g_ms / max(1, g_n)
-    d_launch_ms = d_ms / max(1, d_n)
-    flops_launch = flops_step / max(1, g_n // k)
-    achieved = flops_launch / (g_launch_ms * 1e-3) / 1e12
-    d_achieved = (flops_step / max(1, d_n // k)) / (d_launch_ms * 1e-3) / 1e12
-    log(f"[bench] {ms_step:.2f} ms/step, {value:.1f} MVis/s; gridder {g_launch_ms:.3f} ms/launch "
-        f"({achieved:.2f} TFLOP/s), adder {a_ms / max(1, a_n):.3f} ms, degridder {d_launch_ms:.3f} ms "
-        f"({d_achieved:.2f} TFLOP/s)")
-    tuned = plan.get_tuning()
-    plain_form = None
-    if args.form == "auto":
-        plan.set_tuning(form="plain", blocks_per_cu=0, adder_chunk=tuned["adder_chunk"], degrid_shape="standard")
-        p_ms, _ = timed(args.steps, 1)
-        plain_form = {"ms_per_step": round(p_ms, 4), "value": round(nvis / (p_ms * 1e-3) / 1e6, 3),
-                      "step_ms": dict(timed.dist)}
-        log(f"[bench] plain form: {plain_form}")
-        plan.set_tuning(**tuned)
-
+    leg, res = run_leg(idg, torch, args.workload, args, log)
     result = {
         "metric": "MVis/s grid+degrid, % of FP32 VALU peak; p50/p99 job latency vs plain",
-        "value": round(value, 3),
+        "value": res["value"],
         "unit": "MVis/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "step_ms": step_dist,
+        "ms_per_step": res["ms_per_step"],
+        "step_ms": res["step_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_DESC[args.workload], "nr_visibilities": nvis,
-                   "nr_subgrids": st["nr_subgrids"], "subgrid_size": L, "grid_size": N,
-                   "polarisations": 4, "phase_offsets": "f64", "taper": "PSWF beta=7",
-                   "scratch_bytes": scratch,
-                   "tuning": tuned},
-        "roofline": {"bound": "alu", "kernel": "gridder", "achieved": round(achieved, 3),
-                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                     "traffic": gridder_traffic(args.workload, tuned["grid_form"]), "traffic_unit": "bytes/launch",
-                     "kernels_sha256": kernel_source_hash(),
-                     "work_per_launch": f"{FLOP_PER_VIS_PIX} flop x {nvis} vis x {L * L} pix",
-                     "avg_launch_ms": round(g_launch_ms, 4)},
-        "grid_mvis_s": round(nvis / (grid_ms * 1e-3) / 1e6, 3),
-        "degrid_mvis_s": round(nvis / (degrid_ms * 1e-3) / 1e6, 3),
-        "kernels_ms_per_step": {"gridder": round(g_ms / k, 4), "adder": round(a_ms / k, 4),
-                                "degridder": round(d_ms / k, 4), "zero": round(z_ms / k, 4)},
-        "degridder_roofline": {"achieved": round(d_achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                               "frac": round(d_achieved / FP32_PEAK_TFLOPS, 4)},
-        "plan_ms": round(plan_ms, 1),
-        "plain_form": plain_form,
-        "autotune_ms": tune_info["timings_ms"] if tune_info else None,
+        "config": leg.config(),
+        "roofline": res["roofline"],
         "cpu_baseline": None,
     }
-    result["hbm_stages"] = hbm_stages(idg, torch, plan, grid, stream, a_ms / k, log)
-    if not args.no_wstack and args.workload == "lofar":
-        result["wstack"] = wstack_leg(idg, torch, wl, tuned, log)
-    if args.serve_jobs > 0 and args.workload == "lofar":
-        result["serving"] = serving_leg(wl, dict(uvw=uvw, freqs=freqs, vis=vis, aterms=aterms, taper=taper),
-                                        args.serve_jobs, log)
+    for key in ("gridder_roofline", "degridder_roofline", "grid_mvis_s", "degrid_mvis_s", "kernels_ms_per_step",
+                "plan_ms", "plain_form", "autotune_ms"):
+        result[key] = res[key]
+    if not args.no_hbm_stages:
+        result["hbm_stages"] = hbm_stages(idg, torch, leg.plan, leg.grid, leg.stream,
+                                          res["kernels_ms_per_step"]["adder"], log)
+    head_wl = leg.wl
+    lleg = None
+    if args.workload == "lofar":
+        lleg = leg
+    else:
+        leg.release()
+        if not args.no_lofar:
+            lleg, lres = run_leg(idg, torch, "lofar", args, log)
+            lres["config"] = lleg.config()
+            result["lofar"] = lres
+    if lleg is not None:
+        if not args.no_wstack:
+            result["wstack"] = wstack_leg(idg, torch, lleg.wl, lleg.plan.get_tuning(), log)
+        if args.serve_jobs > 0:
+            result["serving"] = serving_leg(lleg.wl, lleg.dev_inputs(), args.serve_jobs, log)
+        lleg.release()
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline (oracle, ~{args.cpu_budget:.0f} s)")
-        result["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        result["cpu_baseline"] = cpu_baseline(head_wl, args.cpu_budget, args.cpu_procs)
         log(f"[bench] cpu baseline {result['cpu_baseline']}")
     if args.copy_calibration > 0:
         # an elementwise kernel that reads BYTES and writes BYTES (torch's copy_ may use the DMA engines)

@@ -5,7 +5,7 @@
  *
  * The library partitions visibilities into subgrids (§3.2), grids each subgrid
  * by a direct image-domain sum with per-pixel A-terms and taper (§3.3 eq.
- * ShiftedDirectImaging, Algorithm 1, §3.5), transforms it to the uv domain and
+ * ShiftedDirectImaging, Algorithm 1, §3.4), transforms it to the uv domain and
  * adds it to the master grid; degridding runs the adjoint chain (Algorithm 2).
  *
  * Conventions shared by every entry point
@@ -25,7 +25,7 @@
  *  - subgrid image pixel (j, i) is at l = (i - L/2) S / L, m = (j - L/2) S / L,
  *    n' = sqrt(1 - l^2 - m^2) - 1 (§2 pixel positions, §3.3);
  *  - gridding applies c * A_s1^H Y A_s2 per pixel, degridding c * A_s1 B A_s2^H
- *    (the polarised form of §3.5: the scalar kernel c * g_s1^* g_s2 of Algorithm 1
+ *    (the polarised form of §3.4: the scalar kernel c * g_s1^* g_s2 of Algorithm 1
  *    becomes a product of Jones matrices);
  *  - subgrid transform: the centred DFT
  *      V[b][a] = sum_{j,i} I[j][i] exp(-2 pi i ((a-L/2)(i-L/2) + (b-L/2)(j-L/2)) / L),
@@ -96,7 +96,7 @@ typedef struct {
 
 /*
  * Partition the visibilities into subgrids (§3.2 Partitioning, Fig. 2; blocks
- * cut at A-term slot boundaries as in §3.5 Variations).  Host only: nothing is
+ * cut at A-term slot boundaries as in §3.4 Variations).  Host only: nothing is
  * queued on a device (device metadata is uploaded on first use).
  *
  * Each block holds one baseline, a run of at most T_max timesteps inside one
@@ -195,7 +195,7 @@ int idg_plan_get_tuning(idg_plan_t plan, idg_tuning *tuning);
 void idg_plan_destroy(idg_plan_t plan);
 
 /*
- * Image-domain gridding (Algorithm 1 without its last line, §3.3, §3.5): for
+ * Image-domain gridding (Algorithm 1 without its last line, §3.3, §3.4): for
  * every subgrid, the direct sum over its samples of Y_k exp(+2 pi i (du_k l +
  * dv_k m + w_k n')) with du_k = u_k - u_0p computed in float64 and the
  * per-pixel phase in float32; then c * A_s1^H S A_s2 per pixel; the centred

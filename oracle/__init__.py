@@ -5,7 +5,7 @@ method (van der Tol, Veenboer & Offringa, "Image Domain Gridding", A&A 2018):
 the partitioning of visibilities into subgrids (§3.2), the per-subgrid direct
 imaging sum (§3.3, eq. ShiftedDirectImaging; Algorithm 1), the subgrid DFT and
 the adder (Algorithm 1), and the reverse chain (Algorithm 2), with the
-polarised extension of §3.5.  It exists only to check the HIP implementation.
+polarised extension of §3.4.  It exists only to check the HIP implementation.
 
 Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
 may import it.  It shares no code with the HIP library: it computes every step

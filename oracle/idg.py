@@ -11,13 +11,13 @@ the design notes of the repository):
 * Subgrid image pixel (j, i) (row j <-> m, column i <-> l) sits at
   l_i = (i - L/2) S / L, m_j = (j - L/2) S / L -- the pixel positions of §2
   with L_p pixels across S -- and n'_ij = sqrt(1 - l_i^2 - m_j^2) - 1.
-* Polarised data (§3.5): a sample is the 2x2 matrix Y = [[XX, XY], [YX, YY]];
+* Polarised data (§3.4): a sample is the 2x2 matrix Y = [[XX, XY], [YX, YY]];
   an A-term is a 2x2 Jones matrix per (slot, station, pixel), row-major
   [J00, J01, J10, J11].  With stations s1 < s2 of the baseline, gridding
   applies c * A_s1^H Y A_s2 per pixel and degridding applies c * A_s1 B A_s2^H;
   these reduce to c^* y (Algorithm 1) and c I (Algorithm 2) in the scalar case,
   where the per-block kernel is g_s1^* g_s2 (§2, definition of A_k) and the
-  multiplication by the kernel is moved out of the visibility loop (§3.5).
+  multiplication by the kernel is moved out of the visibility loop (§3.4).
 * Subgrid transform (Algorithm 1, "FFT"): the centred forward DFT
   V[b][a] = sum_{j,i} I[j][i] exp(-2 pi i ((a-L/2)(i-L/2) + (b-L/2)(j-L/2)) / L),
   unnormalised.  Degridding (Algorithm 2, "IFFT") uses its conjugate
@@ -80,7 +80,7 @@ def phasor_matrix(du, dv, w, l, m, nprime, sign):
 
 
 def grid_subgrid_image(plan, p, uvw, freqs, vis, aterms, taper):
-    """Subgrid image I_p [4, L, L] before the transform (Algorithm 1, inner loops; §3.5)."""
+    """Subgrid image I_p [4, L, L] before the transform (Algorithm 1, inner loops; §3.4)."""
     N, L, S = plan.grid_size, plan.subgrid_size, plan.image_size
     sub = plan.subgrids[p]
     tc = plan.subgrid_samples(p)

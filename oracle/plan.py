@@ -5,7 +5,7 @@ holding one baseline, several timesteps and several channels, such that the
 support of every visibility in the block lies inside a box of L x L pixels --
 the subgrid -- whose central pixel is (u_0p, v_0p) and whose corner in the
 master grid is (q_0p, r_0p).  Subgrids may overlap and need not cover the grid.
-§3.5 (Variations) adds that blocks may be cut so that one image-domain kernel
+§3.4 (Variations) adds that blocks may be cut so that one image-domain kernel
 (A-term) applies per block.  The paper gives no algorithm beyond the box
 criterion, so this module fixes one deterministic rule; the C++ planner of the
 library implements the same rule independently.

@@ -2,7 +2,7 @@
 //
 //   gridder    direct image-domain sum of a subgrid's visibilities (§3.3 eq.
 //              ShiftedDirectImaging; Algorithm 1 inner loops), A-terms x taper
-//              per pixel (§3.5), centred DFT in LDS (Algorithm 1 "FFT")
+//              per pixel (§3.4), centred DFT in LDS (Algorithm 1 "FFT")
 //   adder      sum of transformed subgrids into the master grid, one
 //              workgroup per grid tile and polarisation (Algorithm 1, add)
 //   degridder  splitter, inverse centred DFT, A-terms x taper, and the

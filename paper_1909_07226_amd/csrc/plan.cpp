@@ -1,6 +1,6 @@
 // Subgrid planner (host).  Partitions the samples of every baseline into blocks
 // whose supports fit an L x L box (§3.2 Partitioning, Fig. 2), never crossing
-// an A-term slot so that one Jones matrix per station applies per block (§3.5).
+// an A-term slot so that one Jones matrix per station applies per block (§3.4).
 //
 // The rule is stated in include/idg.h (idg_plan).  All geometry is float64 and
 // must not be contracted into fused multiply-adds: the plan is an integer

@@ -1,4 +1,4 @@
-// Host-side subgrid plan (partitioning of §3.2 with the A-term cuts of §3.5).
+// Host-side subgrid plan (partitioning of §3.2 with the A-term cuts of §3.4).
 #pragma once
 
 #include <cstdint>

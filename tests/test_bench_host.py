@@ -1,5 +1,6 @@
-"""Host-side logic of bench.py (no GPU): the traffic record and the touched-tile count."""
+"""Host-side logic of bench.py (no GPU): the traffic record, the flop count and the touched-tile count."""
 
+import math
 import os
 
 import numpy as np
@@ -25,31 +26,64 @@ def test_touched_tile_count_matches_brute_force():
         assert bench.touched_tile_count(plan, tile=tile) == len(tiles)
 
 
+def test_algorithmic_flops_terms():
+    # 34 flop per visibility x pixel, 136 per pixel per subgrid, 5 L^2 log2 L^2 per polarisation per subgrid
+    assert bench.algorithmic_flops(10, 0, 32) == 34 * 10 * 1024
+    assert bench.algorithmic_flops(0, 3, 32) == 3 * (136 * 1024 + 5 * 1024 * 10 * 4)
+    assert math.isclose(bench.algorithmic_flops(0, 1, 24), 136 * 576 + 5 * 576 * math.log2(576) * 4)
+    # the SKA-low-like share: 120,570,964 visibilities in 1,965,283 subgrids of 32 x 32
+    assert math.isclose(bench.algorithmic_flops(120570964, 1965283, 32), 4.874e12, rel_tol=1e-3)
+
+
 def test_traffic_record_requires_matching_kernel_source(tmp_path, monkeypatch):
-    record = ("traffic-record: workload=lofar form=persistent kernel=k fetch_kib=1000 write_kib=500 "
-              "fetch_factor=2.0 write_factor=1.0 kernels_sha256={h}\n")
+    record = ("traffic-record: workload=skalow kernel=degridder schedule=persistent/0/standard fetch_kib=1000 "
+              "write_kib=500 fetch_factor=2.0 write_factor=1.0 kernels_sha256={h}\n")
     src = tmp_path / "kernels.hip"
     src.write_text("// kernel source\n")
     monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
     h = bench.kernel_source_hash()
     rec = tmp_path / "record.md"
-    monkeypatch.setattr(bench, "HBM_RECORD", str(rec))
     rec.write_text("# summary\n\n" + record.format(h=h))
-    assert bench.gridder_traffic("lofar", "persistent") == (1000 * 2 + 500) * 1024
-    assert bench.gridder_traffic("lofar", "plain") is None            # other schedule
-    assert bench.gridder_traffic("skalow", "persistent") is None      # other workload
-    src.write_text("// kernel source, changed\n")                      # counters are stale now
-    assert bench.gridder_traffic("lofar", "persistent") is None
+    p = str(rec)
+    assert bench.kernel_traffic("skalow", "degridder", "persistent/0/standard", p) == (1000 * 2 + 500) * 1024
+    assert bench.kernel_traffic("skalow", "degridder", "plain/0/standard", p) is None    # other schedule
+    assert bench.kernel_traffic("skalow", "gridder", "persistent/0/standard", p) is None  # other kernel
+    assert bench.kernel_traffic("lofar", "degridder", "persistent/0/standard", p) is None  # other workload
+    src.write_text("// kernel source, changed\n")                                       # counters are stale now
+    assert bench.kernel_traffic("skalow", "degridder", "persistent/0/standard", p) is None
     os.remove(rec)
-    assert bench.gridder_traffic("lofar", "persistent") is None      # no summary at all
+    assert bench.kernel_traffic("skalow", "degridder", "persistent/0/standard", p) is None  # no summary at all
 
 
-def test_committed_traffic_record_is_parseable():
-    # the committed summary holds one well-formed record (its hash may or may not match the source)
-    with open(bench.HBM_RECORD) as f:
-        lines = [ln for ln in f if ln.startswith("traffic-record:")]
-    assert len(lines) == 1
-    fields = dict(kv.split("=", 1) for kv in lines[0].split()[1:])
-    for key in ("workload", "form", "fetch_kib", "write_kib", "fetch_factor", "write_factor", "kernels_sha256"):
-        assert key in fields
-    assert np.isfinite(float(fields["fetch_kib"])) and float(fields["fetch_factor"]) > 0
+def test_schedule_string():
+    t = dict(grid_form="persistent", degrid_form="plain", grid_blocks_per_cu=0, degrid_blocks_per_cu=2,
+             adder_chunk=64, degrid_shape="wide")
+    assert bench.schedule_string(t, "gridder") == "persistent/0"
+    assert bench.schedule_string(t, "degridder") == "plain/2/wide"
+
+
+def test_committed_traffic_records_are_parseable():
+    # every committed counter summary holds well-formed records (their hashes may or may not match the source)
+    for name in sorted(os.listdir(bench.PROFILES)):
+        if not name.endswith("_hbm_counters.md"):
+            continue
+        with open(os.path.join(bench.PROFILES, name)) as f:
+            lines = [ln for ln in f if ln.startswith("traffic-record:")]
+        for ln in lines:
+            fields = dict(kv.split("=", 1) for kv in ln.split()[1:])
+            for key in ("workload", "kernel", "schedule", "fetch_kib", "write_kib", "fetch_factor", "write_factor",
+                        "kernels_sha256"):
+                assert key in fields, (name, key)
+            assert np.isfinite(float(fields["fetch_kib"])) and float(fields["fetch_factor"]) > 0
+
+
+def test_host_cores_reports_affinity_and_model():
+    aff, model, quota = bench.host_cores()
+    assert aff == len(os.sched_getaffinity(0)) and aff >= 1
+    assert isinstance(model, str) and model
+    assert quota is None or quota > 0
+
+
+def test_image_passes():
+    assert bench.image_passes(512) == 2 and bench.image_passes(1024) == 2
+    assert bench.image_passes(2048) == 3 and bench.image_passes(8192) == 3

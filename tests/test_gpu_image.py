@@ -1,7 +1,8 @@
 """Master grid <-> image on the GPU against the float64 oracle.
 
 * whole transforms at small sizes (both directions, with and without the
-  correction), element by element;
+  correction), element by element, and at N = 2048, the smallest size of the
+  four-step column transform;
 * the workload grid sizes (512, 4096, 8192): sampled pixels / cells that the
   oracle computes one by one, plus the round trip image_to_grid(grid_to_image(g))
   = N^2 g, which holds at any size;
@@ -64,6 +65,26 @@ def test_whole_transforms_match_oracle(N, with_corr):
     assert rms_rel(img, ref) < GRID_RMS_TOL and max_rel(img, ref) < IMAGE_MAX_TOL
     back = _run("image_to_grid", g, cl, cm)
     ref = oim.image_to_grid(g, ocl, ocm)
+    say(f"    image->grid rms {rms_rel(back, ref):.2e} max {max_rel(back, ref):.2e}")
+    assert rms_rel(back, ref) < GRID_RMS_TOL and max_rel(back, ref) < IMAGE_MAX_TOL
+
+
+def test_four_step_whole_array_matches_oracle():
+    # N = 2048 is the smallest size that runs the four-step column transform (two sub-passes with
+    # the gathered row pass): the whole [4, N, N] array, element by element, in both directions
+    require_gpu()
+    N = 2048
+    rng = np.random.default_rng(2048)
+    g = _rand_grid(rng, N)
+    cl, cm = _corr(rng, N)
+    say(f"[image four-step whole array] N={N}")
+    img = _run("grid_to_image", g, cl, cm)
+    ref = oim.grid_to_image(g, cl.astype(np.float64), cm.astype(np.float64))
+    say(f"    grid->image rms {rms_rel(img, ref):.2e} max {max_rel(img, ref):.2e}")
+    assert rms_rel(img, ref) < GRID_RMS_TOL and max_rel(img, ref) < IMAGE_MAX_TOL
+    del img, ref
+    back = _run("image_to_grid", g, cl, cm)
+    ref = oim.image_to_grid(g, cl.astype(np.float64), cm.astype(np.float64))
     say(f"    image->grid rms {rms_rel(back, ref):.2e} max {max_rel(back, ref):.2e}")
     assert rms_rel(back, ref) < GRID_RMS_TOL and max_rel(back, ref) < IMAGE_MAX_TOL
 

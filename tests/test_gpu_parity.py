@@ -4,9 +4,9 @@ Every comparison uses the same seeded inputs on both sides.  Stage tests
 (gridder image, gridder after the transform, batched transform, adder,
 splitter) localise a failure; end-to-end tests cover idg_grid / idg_degrid on
 the tiny workload, cut-down LOFAR-like and SKA-low-like workloads (several
-tiles, ragged time blocks, flags), every supported subgrid size, and the
-full-size LOFAR-like workload on sampled outputs and on a property that holds
-at any size.
+tiles, ragged time blocks, flags) and every supported subgrid size.  The
+full-size workloads, in the schedules the benchmark runs, are covered by
+test_gpu_fullsize.py.
 """
 
 import numpy as np
@@ -366,86 +366,3 @@ def test_adder_chunks_split_long_tile_lists(gpu):
         x0, y0 = oplan.subgrids[p, F["x0"]], oplan.subgrids[p, F["y0"]]
         ref[:, y0:y0 + L, x0:x0 + L] += sub[p]
     assert max_rel(g.cpu().numpy(), ref) < 1e-6
-
-
-# ---------------------------------------------------------------------------
-# full-size LOFAR-like workload (the benchmark configuration)
-
-
-@pytest.fixture(scope="module")
-def lofar_full(gpu):
-    torch, idg = gpu
-    wl = synth.make_workload("lofar")
-    plan = idg.Plan.from_workload(wl)
-    d = to_dev(wl)
-    return wl, plan, d
-
-
-def test_full_lofar_sampled_subgrids(gpu, lofar_full):
-    torch, idg = gpu
-    wl, plan, d = lofar_full
-    say(f"[lofar full] sampled subgrids of {plan.nr_subgrids}")
-    sub, smp = plan.export()
-    from oracle.plan import Plan as OPlan
-    oplan = OPlan(wl.grid_size, wl.image_size, wl.subgrid_size, wl.kernel_size, wl.max_timesteps,
-                  wl.aterm_timesteps, wl.nr_baselines, wl.nr_timesteps, wl.nr_channels, sub, smp.astype(np.int64),
-                  int(sub[:, F["nvis"]].sum()), 0, 0)
-    rng = np.random.default_rng(5)
-    ids = rng.choice(plan.nr_subgrids, 12, replace=False)
-    ids = np.append(ids, np.argmax(sub[:, F["nvis"]]))       # the largest subgrid (several staging rounds)
-    L = wl.subgrid_size
-    out = torch.empty((1, 4, L, L), dtype=torch.complex64, device="cuda")
-    for p in ids:
-        idg.grid_subgrids(plan, d["uvw"], d["freqs"], d["vis"], d["aterms"], d["taper"], int(p), 1, 1, out)
-        idg.sync()
-        ref = oidg.grid_subgrid(oplan, int(p), wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)
-        assert rms_rel(out[0].cpu().numpy(), ref) < GRID_RMS_TOL, p
-
-
-def test_full_lofar_grid_sum_property(gpu, lofar_full):
-    # any size: the sum of a subgrid's uv pixels is L^2 times its image at l = m = 0, i.e.
-    # L^2 c[L/2, L/2] A_s1^H (sum_k Y_k) A_s2 at the centre pixel; summed over all subgrids
-    torch, idg = gpu
-    wl, plan, d = lofar_full
-    say("[lofar full] grid sum property")
-    g = _grid_gpu(torch, idg, wl, plan, d)
-    total = g.to(torch.complex128).sum(dim=(1, 2)).cpu().numpy()
-    sub, smp = plan.export()
-    L = wl.subgrid_size
-    c = float(wl.taper[L // 2, L // 2])
-    ref = np.zeros(4, np.complex128)
-    vis = wl.vis
-    for p in range(sub.shape[0]):
-        bl, off, n = sub[p, F["bl"]], sub[p, F["vis_offset"]], sub[p, F["nvis"]]
-        tc = smp[off:off + n]
-        y = vis[bl, tc[:, 0], tc[:, 1]].astype(np.complex128).sum(0).reshape(2, 2)
-        a1 = wl.aterms[sub[p, F["slot"]], sub[p, F["st1"]], L // 2, L // 2].astype(np.complex128).reshape(2, 2)
-        a2 = wl.aterms[sub[p, F["slot"]], sub[p, F["st2"]], L // 2, L // 2].astype(np.complex128).reshape(2, 2)
-        ref += (np.conj(a1.T) @ y @ a2).reshape(4)
-    ref *= L * L * c
-    say(f"    sum rel err {np.abs(total - ref).max() / np.abs(ref).max():.2e}")
-    assert np.abs(total - ref).max() / np.abs(ref).max() < 1e-5
-
-
-def test_full_lofar_sampled_visibilities(gpu, lofar_full):
-    torch, idg = gpu
-    wl, plan, d = lofar_full
-    say("[lofar full] sampled degridded visibilities")
-    N = wl.grid_size
-    rng = np.random.default_rng(8)
-    gin = torch.complex(torch.randn((4, N, N), generator=torch.Generator().manual_seed(4)),
-                        torch.randn((4, N, N), generator=torch.Generator().manual_seed(5))).to(torch.complex64)
-    gh = gin.numpy()
-    vis = torch.empty(tuple(wl.vis.shape), dtype=torch.complex64, device="cuda")
-    idg.degrid(plan, d["uvw"], d["freqs"], gin.cuda(), d["aterms"], d["taper"], vis)
-    idg.sync()
-    sub, smp = plan.export()
-    from oracle.plan import Plan as OPlan
-    oplan = OPlan(wl.grid_size, wl.image_size, wl.subgrid_size, wl.kernel_size, wl.max_timesteps,
-                  wl.aterm_timesteps, wl.nr_baselines, wl.nr_timesteps, wl.nr_channels, sub, smp.astype(np.int64),
-                  int(sub[:, F["nvis"]].sum()), 0, 0)
-    for p in rng.choice(plan.nr_subgrids, 10, replace=False):
-        ref = oidg.degrid_subgrid(oplan, int(p), wl.uvw, wl.freqs, gh, wl.aterms, wl.taper)
-        tc = oplan.subgrid_samples(int(p))
-        got = vis[int(sub[p, F["bl"]])].cpu().numpy()[tc[:, 0], tc[:, 1]]
-        assert rms_rel(got, ref) < VIS_RMS_TOL, p

@@ -154,7 +154,7 @@ def test_wstack_image_steps_four_step_sampled(w0s):
     scale = np.sqrt(3 * 2.0) * n / (cl.mean() * cm.mean())
     err = np.abs(got - ref).max() / scale
     say(f"    to image sampled err {err:.2e}")
-    assert err < 1e-4
+    assert err < 1e-5          # measured 5-8e-7: a float32 n' at w0 = 4500 (~2.5e-4 rad at the edge) would fail
     im = g[1]
     out = torch.empty((3, 4, n, n), dtype=torch.complex64, device="cuda")
     idg.image_to_wstack(torch.from_numpy(im).cuda(), S2, tl, tm, w0s, out)
@@ -163,7 +163,7 @@ def test_wstack_image_steps_four_step_sampled(w0s):
     ref = oim.image_to_wstack_at(im, w0s, S2, xs, ys, cl.astype(np.float64), cm.astype(np.float64))
     err = np.abs(got - ref).max() / (np.sqrt(2.0) * n * np.mean(1.0 / cl) * np.mean(1.0 / cm))
     say(f"    to layers sampled err {err:.2e}")
-    assert err < 1e-4
+    assert err < 1e-5
 
 
 def test_layered_adjoint_at_scale():
