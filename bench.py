@@ -51,7 +51,7 @@ WORKLOAD_DESC = {
     "tiny": "tiny: 8 stations (28 baselines), 32 x 10 s, 4 ch 150-151 MHz, w=0, L=24, 512^2 grid at 1 arcmin",
 }
 # baseline stride of the oracle's bounded sample (cpu_baseline)
-CPU_SAMPLE_STRIDE = {"skalow": 256, "lofar": 16, "tiny": 1}
+CPU_SAMPLE_STRIDE = {"skalow": 32, "lofar": 16, "tiny": 1}
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1909_07226_amd", "csrc", "kernels.hip")

@@ -65,6 +65,7 @@ struct DevPlan {
   idg::CombineItem *combine = nullptr;
   std::vector<Batch> batches;
   int64_t batch_size = 0, max_slots = 0;
+  int64_t degrid_n_large = 0;  // leading entries of degrid_order above the small-subgrid threshold
 
   ~DevPlan() {
     int cur = -1;
@@ -293,6 +294,8 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
   std::vector<int32_t> degrid_order(static_cast<size_t>(P));
   for (int64_t i = 0; i < P; ++i) degrid_order[size_t(i)] = int32_t(i);
   by_cost(degrid_order, 0);
+  for (int64_t i = 0; i < P; ++i)
+    if (h.subgrids[size_t(degrid_order[size_t(i)])].nvis > idg::degrid_small_threshold()) dp->degrid_n_large = i + 1;
 
   // per scratch batch: gridder order and adder items over tile lists
   dp->batch_size = batch_size_of(p);
@@ -435,6 +438,10 @@ int idg_plan(const idg_params *params, const int32_t *baselines, const double *u
     delete plan;
     return fail(rc, "%s", err.c_str());
   }
+  if (int64_t(plan->host.subgrids.size()) >= (int64_t(1) << 31)) {  // subgrid indices are int32 on the device
+    delete plan;
+    return fail(IDG_EINVAL, "idg_plan: more than 2^31 - 1 subgrids");
+  }
   if (int64_t(plan->host.nr_wlayers) * ((p.grid_size + idg::kAdderTile - 1) / idg::kAdderTile) *
           ((p.grid_size + idg::kAdderTile - 1) / idg::kAdderTile) >= (int64_t(1) << 31)) {
     delete plan;
@@ -564,10 +571,12 @@ static bool degrid_wide(const idg_plan_s *plan) {
   return plan->tuning.degrid_shape == IDG_DEGRID_WIDE && !(plan->host.params.flags & IDG_PHASE_FP32);
 }
 
-static int persistent_blocks(const idg_plan_s *plan, const DevPlan *dp, bool degrid) {
+// small: the degridder's kernel for subgrids of few visibilities
+static int persistent_blocks(const idg_plan_s *plan, const DevPlan *dp, bool degrid, bool small = false) {
   const int L = plan->host.params.subgrid_size;
   const int want = degrid ? plan->tuning.degrid_blocks_per_cu : plan->tuning.grid_blocks_per_cu;
-  const int per_cu = want > 0 ? want : idg::persistent_blocks_per_cu(L, degrid, degrid && degrid_wide(plan));
+  const int per_cu =
+      want > 0 ? want : idg::persistent_blocks_per_cu(L, degrid, degrid && degrid_wide(plan), degrid && small);
   return std::max(1, per_cu * dp->nr_cus);
 }
 
@@ -597,6 +606,7 @@ int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const 
   a.taper = taper_d;
   a.subgrids_out = g.subgrids;
   a.stage = 1;
+  a.pieces = 1;  // the adder reads each tile's piece of a subgrid as one block
   hipError_t err = hipSuccess;
   for (const Batch &b : dp->batches) {
     a.first = b.first;
@@ -620,6 +630,7 @@ int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const 
     ad.ncombine = int32_t(b.ncombine);
     ad.ntx = (p.grid_size + idg::kAdderTile - 1) / idg::kAdderTile;
     ad.grid_size = p.grid_size;
+    ad.pieces = 1;
     {
       StageTimer tm(IDG_STAGE_ADDER, s);
       err = idg::launch_adder(L, ad, s);
@@ -658,28 +669,27 @@ int idg_degrid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, cons
   a.taper = taper_d;
   const int64_t P = int64_t(h.subgrids.size());
   const int L = h.params.subgrid_size;
-  if (plan->tuning.degrid_form == IDG_FORM_PERSISTENT && P > 0) {
-    int32_t *counter = nullptr;
+  if (P == 0) return IDG_OK;
+  a.first = 0;
+  a.count = int32_t(P);
+  if (plan->tuning.degrid_form == IDG_FORM_PERSISTENT) {
+    int32_t *counter = nullptr;  // two queue counters: subgrids above and below the small-subgrid threshold
     HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&counter), 256, s), "idg_degrid: queue counter");
-    a.first = 0;
-    a.count = int32_t(P);
     hipError_t err;
     {
       StageTimer tm(IDG_STAGE_DEGRIDDER, s);
-      err = idg::launch_degridder_persistent(L, a, degrid_wide(plan), dp->degrid_order, counter,
-                                             persistent_blocks(plan, dp, true), s);
+      err = idg::launch_degridder_persistent(L, a, degrid_wide(plan), dp->degrid_order, dp->degrid_n_large, counter,
+                                             persistent_blocks(plan, dp, true), persistent_blocks(plan, dp, true, true),
+                                             s);
     }
     hipError_t ef = hipFreeAsync(counter, s);
     if (err != hipSuccess) return hip_fail(err, "idg_degrid: launch");
     HIP_TRY(ef, "idg_degrid: counter release");
     return IDG_OK;
   }
-  for (int64_t f = 0; f < P; f += (int64_t(1) << 30)) {
-    a.first = f;
-    a.count = int32_t(std::min<int64_t>(P - f, int64_t(1) << 30));
-    StageTimer tm(IDG_STAGE_DEGRIDDER, s);
-    HIP_TRY(idg::launch_degridder(L, a, degrid_wide(plan), s), "idg_degrid: launch");
-  }
+  StageTimer tm(IDG_STAGE_DEGRIDDER, s);
+  HIP_TRY(idg::launch_degridder(L, a, degrid_wide(plan), dp->degrid_order, dp->degrid_n_large, s),
+          "idg_degrid: launch");
   return IDG_OK;
 }
 

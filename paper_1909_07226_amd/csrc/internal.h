@@ -43,6 +43,7 @@ struct KernelArgs {
   int32_t stage;       // gridder: 0 = image after A-terms and taper, 1 = after the DFT
   int32_t phase_fp32;  // 1: subgrid offsets in float32 (precision study)
   int32_t chan_recur;  // 1: channel frequencies are uniformly spaced (phasor recurrence over channels)
+  int32_t pieces;      // gridder: 1 = store subgrids in the adder's tile-piece layout, 0 = [4][L][L]
 };
 
 // Adder tile: TILE x TILE pixels of one polarisation.
@@ -69,18 +70,25 @@ struct AdderArgs {
   float2 *grid;                // [4][N][N]
   float2 *partials;            // [slots][4][TILE*TILE]
   int32_t nitems, ncombine, ntx, grid_size;
+  int32_t pieces;              // 1: subgrids_in in the tile-piece layout of the gridder, 0: [4][L][L]
 };
 
 bool supported_subgrid_size(int L);
 
 hipError_t launch_gridder(int L, const KernelArgs &a, hipStream_t s);
-hipError_t launch_degridder(int L, const KernelArgs &a, bool wide, hipStream_t s);
-// persistent forms: `order` holds a.count items, *queue_head is zeroed by the launcher
+// Degridder: `order` holds a.count global subgrid indices sorted by visibility count, costliest
+// first; its first n_large items have more than degrid_small_threshold() visibilities (they run the
+// visibility-per-lane kernel, the rest the pixel-per-lane kernel).
+int degrid_small_threshold();
+hipError_t launch_degridder(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_large,
+                            hipStream_t s);
+// persistent forms: `order` holds a.count items; the gridder's *queue_head (one counter) and the
+// degridder's queue_head[0..1] (large and small subgrids) are zeroed by the launcher
 hipError_t launch_gridder_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
                                      int nblocks, hipStream_t s);
-hipError_t launch_degridder_persistent(int L, const KernelArgs &a, bool wide, const int32_t *order,
-                                       int32_t *queue_head, int nblocks, hipStream_t s);
-int persistent_blocks_per_cu(int L, bool degrid, bool wide);
+hipError_t launch_degridder_persistent(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_large,
+                                       int32_t *queue_head, int nblocks_large, int nblocks_small, hipStream_t s);
+int persistent_blocks_per_cu(int L, bool degrid, bool wide, bool small);
 hipError_t launch_adder(int L, const AdderArgs &a, hipStream_t s);
 hipError_t launch_splitter(int L, const DevSubgrid *subgrids, int64_t first, int64_t count, const float2 *grid,
                            int grid_size, float2 *out, hipStream_t s);

@@ -382,6 +382,27 @@ __device__ __forceinline__ void lds_centred_dft_one_thread_per_line(float2 *sg, 
 }
 
 // ---------------------------------------------------------------------------
+// Tile-piece layout of a transformed subgrid in the gridder's scratch.  The
+// adder's tiles (kAdderTile x kAdderTile, aligned to the grid) cut a subgrid
+// with corner (x0, y0) into up to 3 x 3 pieces; the subgrid is stored piece by
+// piece (row bands top to bottom, pieces left to right, each piece row-major),
+// so that the workgroup that owns a tile reads each of its pieces as one
+// contiguous block and no cache line is shared by two tiles' pieces except at
+// piece ends.  Element (b, a) (row, column) of a subgrid whose corner lies at
+// (ox, oy) = (x0, y0) mod kAdderTile:
+//   row band  bi = (b + oy) / T, rows [rs, rs + h) of the subgrid;
+//   column    ci = (a + ox) / T, columns [cs, cs + w);
+//   offset    rs L + h cs + (b - rs) w + (a - cs).
+template <int L>
+__device__ __forceinline__ int piece_index(int b, int a, int ox, int oy) {
+  constexpr int T = kAdderTile;
+  const int bi = (b + oy) / T, ci = (a + ox) / T;
+  const int rs = bi == 0 ? 0 : bi * T - oy, cs = ci == 0 ? 0 : ci * T - ox;
+  const int h = min(L, (bi + 1) * T - oy) - rs, w = min(L, (ci + 1) * T - ox) - cs;
+  return rs * L + h * cs + (b - rs) * w + (a - cs);
+}
+
+// ---------------------------------------------------------------------------
 // Gridder: PPT pixels per thread.  Plain form: one workgroup per subgrid.
 // Persistent form: a fixed grid of workgroups pulls subgrids from a work
 // queue (a device counter over a cost-sorted list) until the list is empty.
@@ -560,10 +581,14 @@ __device__ __forceinline__ void grid_one(const KernelArgs &a, int local, Gridder
   if (a.stage == 1) lds_centred_dft<L, NT, false>(s_sg, sm.tw);
 
   float2 *out = a.subgrids_out + int64_t(local) * 4 * NPIX;
+  const int ox = d.x0 % kAdderTile, oy = d.y0 % kAdderTile;
 #pragma unroll
-  for (int r = 0; r < PPT; ++r)
+  for (int r = 0; r < PPT; ++r) {
+    const int pix = tid + r * NT;
+    const int o = a.pieces ? piece_index<L>(pix / L, pix % L, ox, oy) : pix;
 #pragma unroll
-    for (int pol = 0; pol < 4; ++pol) out[pol * NPIX + tid + r * NT] = s_sg[SgLayout<L>::idx(pol, tid + r * NT)];
+    for (int pol = 0; pol < 4; ++pol) out[pol * NPIX + o] = s_sg[SgLayout<L>::idx(pol, pix)];
+  }
 }
 
 template <int L, bool FP32_PHASE>
@@ -611,11 +636,17 @@ gridder_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_hea
 // added in LDS at the end.  V and G are chosen per subgrid to fill the waves.
 
 constexpr int kDegridPartCap = 192;  // G * K_p limit of the partial-sum buffer (32 bytes each)
+constexpr int kDegridSmallK = 128;  // subgrids with at most this many visibilities take the pixel-owner path
+constexpr int kDegridSmallNB = 4;  // visibilities per cross-lane reduction
+
 
 template <int L>
 struct DegridderSmem {
   static constexpr bool LMN_LDS = L <= 24;  // larger subgrids read the pixel coordinates through the cache
-  float2 sg[SgLayout<L>::SIZE];             // SgLayout<L>, then [NPIX][4] after the A-terms
+  // the small-subgrid path reuses sg for its staged offsets and per-wave sums (float2 units)
+  static constexpr int SMALL = (2 * kDegridSmallK * 16 + (Cfg<L>::NT / 64) * kDegridSmallK * 32) / 8;
+  static constexpr int SG = SgLayout<L>::SIZE > SMALL ? SgLayout<L>::SIZE : SMALL;
+  float2 sg[SG];                            // SgLayout<L>, then [NPIX][4] after the A-terms
   float4 lmn[LMN_LDS ? L * L : 1];
   float2 tw[L];
   float4 part[2 * kDegridPartCap];          // [G][K] partial sums, 4 complex each
@@ -772,11 +803,192 @@ __device__ __forceinline__ void degrid_tasks(const KernelArgs &a, const DevSubgr
   }
 }
 
+// ---------------------------------------------------------------------------
+// Small subgrids (few visibilities): lanes own pixels, as in the gridder.  The
+// visibilities' offsets are staged in LDS and broadcast; for each visibility
+// every lane sums B * conj(E) over its PPT pixels, and each wave adds the
+// partial sums of NB visibilities across its 64 lanes with cross-lane moves
+// (no LDS); the waves' sums are added in LDS at the end.  Per visibility x
+// pixel the LDS traffic is that of the gridder (one staged offset per
+// visibility), where the visibility-per-lane tasks read two pixel values and
+// the pixel coordinates for every (pixel, lane group) pair.
+
+
+// Reduce-scatter of M = 32 or 64 values across the 64 lanes of a wave: on return
+// lane l holds the sum over all lanes of v[l] (M = 64) or of v[l >> 1] (M = 32).
+// Each step halves the values a lane holds: the lane keeps the half selected by
+// one bit of its index and adds the same half from the lane that differs in
+// that bit (bit 5: lanes 32 apart, permlane32 swap; bit 4: rows of 16,
+// permlane16 swap; bits 3, 2, 1 within a row by DPP: rotate by 8, mirror within
+// 8, quad permute; bit 0 for M = 32: quad permute, both lanes keep the total).
+template <int M>
+__device__ __forceinline__ float wave_reduce_scatter(float (&v)[M]) {
+  static_assert(M == 32 || M == 64, "32 or 64 values");
+  const int lane = threadIdx.x & 63;
+  int h = M / 2;
+  // bit 5: the swap leaves lanes 0-31 with (x_lo, y_lo) and lanes 32-63 with (x_hi, y_hi) split over the
+  // two registers, so one addition gives index i on the lower and i + h on the upper half
+#pragma unroll
+  for (int i = 0; i < M / 2; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + M / 2]), false,
+                                                    false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  h = M / 4;
+  // bit 4: the same with rows of 16 lanes (odd rows of the first register swap with even rows of the second)
+#pragma unroll
+  for (int i = 0; i < M / 4; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + M / 4]), false,
+                                                    false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  (void)h;
+  // bits 3, 2, 1: DPP within a row of 16 lanes; the partner differs in the step's bit
+#define IDG_DPP_STEP(BIT, CTRL, HALF)                                                                     \
+  {                                                                                                       \
+    const bool up = (lane >> (BIT)) & 1;                                                                  \
+    _Pragma("unroll") for (int i = 0; i < (HALF); ++i) {                                                  \
+      const float keep = up ? v[i + (HALF)] : v[i];                                                       \
+      const float send = up ? v[i] : v[i + (HALF)];                                                       \
+      v[i] = keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), (CTRL), 0xf, 0xf, \
+                                                               false));                                   \
+    }                                                                                                     \
+  }
+  IDG_DPP_STEP(3, 0x128, M / 8)  // row_ror:8: lane i <-> i ^ 8 within the row
+  IDG_DPP_STEP(2, 0x141, M / 16)  // row_half_mirror: lane i <-> 7 - i within 8 (differs in bit 2)
+  IDG_DPP_STEP(1, 0x4E, M / 32)   // quad_perm [2, 3, 0, 1]: lane i <-> i ^ 2
+#undef IDG_DPP_STEP
+  if constexpr (M == 64) {
+    const bool up = lane & 1;
+    const float keep = up ? v[1] : v[0];
+    const float send = up ? v[0] : v[1];
+    return keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), 0xB1, 0xf, 0xf, false));
+  } else {
+    return v[0] + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[0]), 0xB1, 0xf, 0xf, false));
+  }
+}
+
+// Degrid subgrid d (K <= kDegridSmallK visibilities) with this thread's pixels' polarised values b (after the
+// A-terms and taper) in registers.  `smem` is free LDS of at least kDegridSmallK * 32 + W * kDegridSmallK * 32
+// bytes.  Starts after a barrier that freed smem; ends with every thread past its last LDS read.
+template <int L, bool FP32_PHASE>
+__device__ __forceinline__ void degrid_small(const KernelArgs &a, const DevSubgrid &d,
+                                             const float2 (&b)[L * L / Cfg<L>::NT][4], float4 *smem, double u0,
+                                             double v0) {
+  constexpr int NT = Cfg<L>::NT, PPT = L * L / NT, W = NT / 64, NB = kDegridSmallNB, KS = kDegridSmallK;
+  float4 *s_uvw = smem;                           // [KS] offsets (x, y, z) and run length (w)
+  float4 *s_step = smem + KS;                     // [KS] channel steps of run starts
+  float *s_red = reinterpret_cast<float *>(smem + 2 * KS);  // [W][KS][8] per-wave sums
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int K = d.nvis;
+  const bool recur = !FP32_PHASE && a.chan_recur != 0;
+  for (int k = tid; k < K; k += NT) {
+    const uint32_t *smp = a.samples + d.vis_offset;
+    const uint32_t pk = smp[k];
+    const int dc = int(pk & 0xffffu);
+    const int t = d.t0 + int(pk >> 16), c = d.c0 + dc;
+    const double *q = a.uvw + (int64_t(d.bl) * a.nr_timesteps + t) * 3;
+    const double s = a.freqs[c] / kC0;
+    // channel runs as in the gridder: a run continues while the next sample is the next channel of the
+    // same timestep, cut every kChanRun channels
+    int len = 0;
+    const bool cont_prev = recur && k > 0 && smp[k - 1] == pk - 1u && dc % kChanRun != 0;
+    if (!cont_prev) {
+      len = 1;
+      if (recur)
+        while (k + len < K && smp[k + len] == pk + uint32_t(len) && (dc + len) % kChanRun != 0) ++len;
+    }
+    if (FP32_PHASE) {
+      const float sf = float(s);
+      s_uvw[k] = make_float4(float(q[0]) * sf, float(q[1]) * sf, float(q[2]) * sf, __int_as_float(len));
+    } else {
+      s_uvw[k] = make_float4(float(q[0] * s - u0), float(q[1] * s - v0), float(q[2] * s - d.w0),
+                             __int_as_float(len));
+    }
+    if (len > 1) {
+      const double ds = (a.freqs[c + 1] - a.freqs[c]) / kC0;
+      s_step[k] = make_float4(float(q[0] * ds), float(q[1] * ds), float(q[2] * ds), 0.0f);
+    }
+  }
+  float pl[PPT], pm[PPT], pn[PPT], p0[PPT];
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const float4 q = a.lmn[tid + r * NT];
+    pl[r] = q.x;
+    pm[r] = q.y;
+    pn[r] = q.z;
+    p0[r] = FP32_PHASE ? float(u0) * q.x + float(v0) * q.y + float(d.w0) * q.z : 0.0f;
+  }
+  __syncthreads();
+  float2 ph[PPT], st[PPT];
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) ph[r] = st[r] = make_float2(1.0f, 0.0f);
+  for (int k0 = 0; k0 < K; k0 += NB) {
+    float y[NB * 8];
+#pragma unroll
+    for (int i = 0; i < NB * 8; ++i) y[i] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int k = k0 + j;
+      if (k < K) {
+        const float4 o = s_uvw[k];
+        const int len = __builtin_amdgcn_readfirstlane(__float_as_int(o.w));
+        if (len > 0) {  // run start (or no run): sin and cos
+#pragma unroll
+          for (int r = 0; r < PPT; ++r) {
+            float f = o.x * pl[r] + o.y * pm[r] + o.z * pn[r];
+            if (FP32_PHASE) f -= p0[r];
+            f = __builtin_amdgcn_fractf(f);
+            ph[r] = make_float2(__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f));
+          }
+          if (len > 1) {
+            const float4 q = s_step[k];
+#pragma unroll
+            for (int r = 0; r < PPT; ++r) {
+              const float f = __builtin_amdgcn_fractf(q.x * pl[r] + q.y * pm[r] + q.z * pn[r]);
+              st[r] = make_float2(__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f));
+            }
+          }
+        } else {  // next channel of the run
+#pragma unroll
+          for (int r = 0; r < PPT; ++r) ph[r] = cmul(ph[r], st[r]);
+        }
+        // y_k += B * exp(-i phase) = B * conj(E)
+#pragma unroll
+        for (int r = 0; r < PPT; ++r)
+#pragma unroll
+          for (int pol = 0; pol < 4; ++pol) {
+            float2 acc = make_float2(y[j * 8 + 2 * pol], y[j * 8 + 2 * pol + 1]);
+            cmac(acc, b[r][pol].x, b[r][pol].y, ph[r].x, -ph[r].y);
+            y[j * 8 + 2 * pol] = acc.x;
+            y[j * 8 + 2 * pol + 1] = acc.y;
+          }
+      }
+    }
+    const float s = wave_reduce_scatter<NB * 8>(y);
+    // lane l holds component (l & 7) of visibility k0 + (l >> 3)  (NB = 8) or (l >> 1): (l >> 4), ((l >> 1) & 7)
+    const int idx = NB * 8 == 64 ? lane : lane >> 1;
+    const int k = k0 + idx / 8;
+    if (k < K && (NB * 8 == 64 || (lane & 1) == 0)) s_red[(wave * KS + k) * 8 + idx % 8] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < K * 8; e += NT) {
+    const int k = e / 8, comp = e % 8;
+    float sum = s_red[k * 8 + comp];
+#pragma unroll
+    for (int w = 1; w < W; ++w) sum += s_red[(w * KS + k) * 8 + comp];
+    reinterpret_cast<float *>(a.vis_out + degrid_out_index(a, d, k))[comp] = sum;
+  }
+}
+
 // Degrid plan subgrid p (global index) into a.vis_out.  The caller has loaded
 // sm.tw and sm.lmn and synchronises before reusing shared memory.  WIDE: tasks
 // of full-wave lane groups run in the split shape (twice the visibilities per
-// lane, two pixel halves per wave), which needs more registers.
-template <int L, bool FP32_PHASE, bool WIDE>
+// lane, two pixel halves per wave), which needs more registers.  SMALL: the
+// subgrid has at most kDegridSmallK visibilities and takes the pixel-owner
+// path; the two paths are separate kernels, so that each gets its own
+// register allocation.
+template <int L, bool FP32_PHASE, bool WIDE, bool SMALL>
 __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, DegridderSmem<L> &sm) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT, W = NT / 64;
   const int tid = threadIdx.x;
@@ -811,6 +1023,14 @@ __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, Degri
     apply_aterms_degrid(J1, J2, a.taper[pix], b[r]);
   }
   __syncthreads();
+  const int K = d.nvis;
+  const double S = a.image_size;
+  const double u0 = double(d.x0 + L / 2 - N / 2) / S;
+  const double v0 = double(d.y0 + L / 2 - N / 2) / S;
+  if constexpr (SMALL) {
+    degrid_small<L, FP32_PHASE>(a, d, b, reinterpret_cast<float4 *>(sm.sg), u0, v0);
+    return;
+  }
   float4 *s_b = reinterpret_cast<float4 *>(sm.sg);  // [NPIX][2] = 4 complex per pixel
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
@@ -823,7 +1043,6 @@ __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, Degri
   // lane groups of Q lanes (small subgrids use groups of 32 or 16 so that lanes are not idle),
   // visibilities per lane V and pixel shares G (a power of two): fill the W * 64/Q lane groups
   // with tasks first, then prefer the largest V (fewest LDS reads per visibility)
-  const int K = d.nvis;
   const int Q = K >= 64 ? 64 : (K > 16 ? 32 : 16);
   const int slots = W * (64 / Q);
   const int nq = (K + Q - 1) / Q;
@@ -841,9 +1060,6 @@ __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, Degri
       nchunks = nc;
     }
   }
-  const double S = a.image_size;
-  const double u0 = double(d.x0 + L / 2 - N / 2) / S;
-  const double v0 = double(d.y0 + L / 2 - N / 2) / S;
   // WIDE: full-wave groups (Q = 64) run as two 32-lane halves over half the pixels each, with
   // twice the visibilities per lane: the same visibilities per task, fewer phasors and pixel
   // reads per visibility
@@ -905,17 +1121,28 @@ constexpr int degrid_min_waves() {
   return L == 32 ? (WIDE ? 3 : 4) : 1;
 }
 
+// Plain form: one workgroup per item order[blockIdx.x] (a.count items).  Subgrids
+// with more than kDegridSmallK visibilities run degridder_kernel, the others
+// degridder_small_kernel; the host passes each its part of the cost-sorted list.
 template <int L, bool FP32_PHASE, bool WIDE>
 __global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(degrid_min_waves<L, WIDE>())))
-degridder_kernel(KernelArgs a) {
+degridder_kernel(KernelArgs a, const int32_t *order) {
   __shared__ DegridderSmem<L> sm;
   degrid_load_tables<L>(a, sm);
-  degrid_one<L, FP32_PHASE, WIDE>(a, a.first + blockIdx.x, sm);
+  degrid_one<L, FP32_PHASE, WIDE, false>(a, order[blockIdx.x], sm);
+}
+
+template <int L, bool FP32_PHASE>
+__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(degrid_min_waves<L, false>())))
+degridder_small_kernel(KernelArgs a, const int32_t *order) {
+  __shared__ DegridderSmem<L> sm;
+  degrid_load_tables<L>(a, sm);
+  degrid_one<L, FP32_PHASE, false, true>(a, order[blockIdx.x], sm);
 }
 
 // Persistent form: items order[0 .. count-1] (global subgrid indices, costliest
 // first) through the counter *queue_head (zero before the launch).
-template <int L, bool FP32_PHASE, bool WIDE>
+template <int L, bool FP32_PHASE, bool WIDE, bool SMALL>
 __global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(degrid_min_waves<L, WIDE>())))
 degridder_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_head) {
   __shared__ DegridderSmem<L> sm;
@@ -925,10 +1152,12 @@ degridder_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_h
     __syncthreads();
     const int item = sm.next;
     if (item >= a.count) break;
-    degrid_one<L, FP32_PHASE, WIDE>(a, order[item], sm);
+    degrid_one<L, FP32_PHASE, WIDE, SMALL>(a, order[item], sm);
     __syncthreads();
   }
 }
+
+int degrid_small_threshold() { return kDegridSmallK; }
 
 // ---------------------------------------------------------------------------
 // Adder: one workgroup per (work item, polarisation).  A work item is a grid
@@ -968,10 +1197,11 @@ __global__ void __launch_bounds__(256) adder_kernel(AdderArgs a) {
         const int ia = x - d.x0;
         if (ia >= 0 && ia < L) {
           const float2 *sp = a.subgrids_in + (int64_t(s) * 4 + pol) * NPIX;
+          const int ox = d.x0 % T, oy = d.y0 % T;
 #pragma unroll
           for (int k = 0; k < PER; ++k) {
             const int jb = ty * T + py + k * ROWS - d.y0;
-            if (jb >= 0 && jb < L) v[u][k] = sp[jb * L + ia];
+            if (jb >= 0 && jb < L) v[u][k] = sp[a.pieces ? piece_index<L>(jb, ia, ox, oy) : jb * L + ia];
           }
         }
       }
@@ -1024,7 +1254,7 @@ __global__ void __launch_bounds__(256) combine_kernel(AdderArgs a) {
 }
 
 __global__ void zero_counter_kernel(int32_t *p) {
-  if (threadIdx.x == 0) p[0] = 0;
+  if (threadIdx.x < 2) p[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1114,50 +1344,81 @@ hipError_t launch_gridder_persistent(int L, const KernelArgs &a, const int32_t *
   return hipGetLastError();
 }
 
-// The all-float32 phase variant has no wide form.
-hipError_t launch_degridder(int L, const KernelArgs &a, bool wide, hipStream_t s) {
-  if (a.count <= 0) return hipSuccess;
+// The all-float32 phase variant has no wide form.  order: the cost-sorted list, its first n_large
+// items with more than kDegridSmallK visibilities.
+hipError_t launch_degridder(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_large,
+                            hipStream_t s) {
+  const int64_t n_small = a.count - n_large;
   IDG_DISPATCH_L(L, {
-    if (a.phase_fp32)
-      hipLaunchKernelGGL((degridder_kernel<LL, true, false>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
-    else if (wide)
-      hipLaunchKernelGGL((degridder_kernel<LL, false, true>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
-    else
-      hipLaunchKernelGGL((degridder_kernel<LL, false, false>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
+    if (n_large > 0) {
+      if (a.phase_fp32)
+        hipLaunchKernelGGL((degridder_kernel<LL, true, false>), dim3(unsigned(n_large)), dim3(Cfg<LL>::NT), 0, s, a,
+                           order);
+      else if (wide)
+        hipLaunchKernelGGL((degridder_kernel<LL, false, true>), dim3(unsigned(n_large)), dim3(Cfg<LL>::NT), 0, s, a,
+                           order);
+      else
+        hipLaunchKernelGGL((degridder_kernel<LL, false, false>), dim3(unsigned(n_large)), dim3(Cfg<LL>::NT), 0, s, a,
+                           order);
+    }
+    if (n_small > 0) {
+      if (a.phase_fp32)
+        hipLaunchKernelGGL((degridder_small_kernel<LL, true>), dim3(unsigned(n_small)), dim3(Cfg<LL>::NT), 0, s, a,
+                           order + n_large);
+      else
+        hipLaunchKernelGGL((degridder_small_kernel<LL, false>), dim3(unsigned(n_small)), dim3(Cfg<LL>::NT), 0, s, a,
+                           order + n_large);
+    }
   });
   return hipGetLastError();
 }
 
-hipError_t launch_degridder_persistent(int L, const KernelArgs &a, bool wide, const int32_t *order,
-                                       int32_t *queue_head, int nblocks, hipStream_t s) {
+// queue_head: two counters (large and small subgrids), zeroed here.
+hipError_t launch_degridder_persistent(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_large,
+                                       int32_t *queue_head, int nblocks_large, int nblocks_small, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, queue_head);
+  KernelArgs al = a, as = a;
+  al.count = int32_t(n_large);
+  as.count = int32_t(a.count - n_large);
   IDG_DISPATCH_L(L, {
-    if (a.phase_fp32)
-      hipLaunchKernelGGL((degridder_persistent_kernel<LL, true, false>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a,
-                         order, queue_head);
-    else if (wide)
-      hipLaunchKernelGGL((degridder_persistent_kernel<LL, false, true>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a,
-                         order, queue_head);
-    else
-      hipLaunchKernelGGL((degridder_persistent_kernel<LL, false, false>), dim3(nblocks), dim3(Cfg<LL>::NT), 0, s, a,
-                         order, queue_head);
+    if (al.count > 0) {
+      if (a.phase_fp32)
+        hipLaunchKernelGGL((degridder_persistent_kernel<LL, true, false, false>), dim3(nblocks_large),
+                           dim3(Cfg<LL>::NT), 0, s, al, order, queue_head);
+      else if (wide)
+        hipLaunchKernelGGL((degridder_persistent_kernel<LL, false, true, false>), dim3(nblocks_large),
+                           dim3(Cfg<LL>::NT), 0, s, al, order, queue_head);
+      else
+        hipLaunchKernelGGL((degridder_persistent_kernel<LL, false, false, false>), dim3(nblocks_large),
+                           dim3(Cfg<LL>::NT), 0, s, al, order, queue_head);
+    }
+    if (as.count > 0) {
+      if (a.phase_fp32)
+        hipLaunchKernelGGL((degridder_persistent_kernel<LL, true, false, true>), dim3(nblocks_small),
+                           dim3(Cfg<LL>::NT), 0, s, as, order + n_large, queue_head + 1);
+      else
+        hipLaunchKernelGGL((degridder_persistent_kernel<LL, false, false, true>), dim3(nblocks_small),
+                           dim3(Cfg<LL>::NT), 0, s, as, order + n_large, queue_head + 1);
+    }
   });
   return hipGetLastError();
 }
 
-int persistent_blocks_per_cu(int L, bool degrid, bool wide) {
+int persistent_blocks_per_cu(int L, bool degrid, bool wide, bool small) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (L) {
-#define IDG_OCC(LL)                                                                                           \
-  case LL:                                                                                                    \
-    e = !degrid ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gridder_persistent_kernel<LL, false>,    \
-                                                               Cfg<LL>::NT, 0)                              \
-        : wide ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, degridder_persistent_kernel<LL, false, true>, \
-                                                              Cfg<LL>::NT, 0)                               \
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, degridder_persistent_kernel<LL, false, false>, \
-                                                              Cfg<LL>::NT, 0);                              \
+#define IDG_OCC(LL)                                                                                            \
+  case LL:                                                                                                     \
+    e = !degrid ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gridder_persistent_kernel<LL, false>,     \
+                                                               Cfg<LL>::NT, 0)                               \
+        : small ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                               \
+                      &n, degridder_persistent_kernel<LL, false, false, true>, Cfg<LL>::NT, 0)               \
+        : wide  ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                               \
+                      &n, degridder_persistent_kernel<LL, false, true, false>, Cfg<LL>::NT, 0)               \
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                               \
+                      &n, degridder_persistent_kernel<LL, false, false, false>, Cfg<LL>::NT, 0);             \
     break;
     IDG_OCC(8)
     IDG_OCC(16)
