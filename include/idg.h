@@ -63,7 +63,7 @@ enum {
   IDG_EINVAL = -1, /* invalid argument or inconsistent sizes */
   IDG_ENOMEM = -2, /* host or device allocation failed */
   IDG_EHIP = -3,   /* HIP runtime or launch error */
-  IDG_ERANGE = -4, /* IDG_STRICT is set and some unflagged samples would be dropped */
+  IDG_ERANGE = -4, /* a size beyond a fixed limit, or IDG_STRICT and some samples would be dropped */
   IDG_ESTATE = -5  /* call not valid in the current state */
 };
 
@@ -220,6 +220,28 @@ void idg_plan_destroy(idg_plan_t plan);
  */
 int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
              const idg_cf32 *aterms_d, const float *taper_d, idg_cf32 *grid_d, void *stream);
+
+/*
+ * idg_grid without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Arguments, arithmetic and result are those of idg_grid (the
+ * same kernels and batches: bitwise the same grid).  Its scratch is a fixed
+ * device array of IDG_NOALLOC_SCRATCH_BYTES compiled into the library, one per
+ * GPU, held from the first call on that GPU until the process ends.  Every
+ * call on a GPU uses that GPU's array: calls that overlap on one GPU (other
+ * streams or threads) race and must be ordered by the caller.  Limits:
+ *   - one batch of the plan must fit: 256 bytes + the adder's partial tiles +
+ *     4 L^2 x 8 bytes per subgrid of a batch (plan with params.scratch_bytes
+ *     of at most about 120 MiB); otherwise IDG_ERANGE, nothing launched;
+ *   - the plan's device copy must already exist on the current device (an
+ *     earlier idg_grid, idg_degrid or idg_grid_subgrids call with the plan on
+ *     this device makes it; idg_plan_set_tuning with a new adder_chunk drops
+ *     it); otherwise IDG_ESTATE, nothing launched.
+ * Errors: IDG_EINVAL (NULL pointer), IDG_ESTATE, IDG_ERANGE, IDG_EHIP.
+ */
+#define IDG_NOALLOC_SCRATCH_BYTES (128LL << 20)
+int idg_grid_noalloc(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
+                     const idg_cf32 *aterms_d, const float *taper_d, idg_cf32 *grid_d, void *stream);
 
 /*
  * Image-domain degridding (Algorithm 2 after its first two lines): for every

@@ -11,11 +11,13 @@ from ._lib import (  # noqa: F401
     IDG_STRICT,
     IDGError,
     LIB_PATH,
+    NOALLOC_SCRATCH_BYTES,
     Plan,
     SUBGRID_FIELDS,
     add_subgrids,
     degrid,
     grid,
+    grid_noalloc,
     grid_subgrids,
     grid_to_image,
     image_to_grid,

@@ -23,7 +23,9 @@ EXPORTED = ("idg_plan", "idg_plan_stats", "idg_plan_export", "idg_plan_destroy",
             "idg_grid_subgrids", "idg_subgrid_fft", "idg_add_subgrids", "idg_split_subgrids", "idg_sync",
             "idg_last_error", "idg_version", "idg_profile", "idg_profile_read", "idg_plan_set_tuning",
             "idg_plan_get_tuning", "idg_grid_to_image", "idg_image_to_grid", "idg_taper_optimal",
-            "idg_taper_correction", "idg_plan_wlayers", "idg_wstack_to_image", "idg_image_to_wstack")
+            "idg_taper_correction", "idg_plan_wlayers", "idg_wstack_to_image", "idg_image_to_wstack",
+            "idg_grid_noalloc")
+NOALLOC_SCRATCH_BYTES = 128 << 20          # IDG_NOALLOC_SCRATCH_BYTES
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 DEGRID_STANDARD, DEGRID_WIDE = 0, 1
 STAGES = ("gridder", "adder", "degridder", "zero")
@@ -72,6 +74,7 @@ def lib():
         L.idg_plan_destroy.argtypes = [vp]
         L.idg_plan_destroy.restype = None
         L.idg_grid.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.idg_grid_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.idg_degrid.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.idg_grid_subgrids.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, i32, vp, vp]
         L.idg_subgrid_fft.argtypes = [vp, i64, i32, i32, vp]
@@ -262,6 +265,16 @@ def grid(plan, uvw_d, freqs_d, vis_d, aterms_d, taper_d, grid_d, stream=None):
     u, f, a, t = _common(plan, uvw_d, freqs_d, aterms_d, taper_d)
     check(lib().idg_grid(plan.handle, u, f, _dev_ptr(vis_d, torch.complex64, sh["vis"], "vis"), a, t,
                          _dev_ptr(grid_d, torch.complex64, sh["grid"], "grid"), _stream_ptr(stream)))
+
+
+def grid_noalloc(plan, uvw_d, freqs_d, vis_d, aterms_d, taper_d, grid_d, stream=None):
+    """idg_grid_noalloc: idg_grid with the library's fixed device scratch (no allocation).  The plan must
+    already have a device copy on this device and batches that fit NOALLOC_SCRATCH_BYTES."""
+    import torch
+    sh = plan.shapes()
+    u, f, a, t = _common(plan, uvw_d, freqs_d, aterms_d, taper_d)
+    check(lib().idg_grid_noalloc(plan.handle, u, f, _dev_ptr(vis_d, torch.complex64, sh["vis"], "vis"), a, t,
+                                 _dev_ptr(grid_d, torch.complex64, sh["grid"], "grid"), _stream_ptr(stream)))
 
 
 def degrid(plan, uvw_d, freqs_d, grid_d, aterms_d, taper_d, vis_d, stream=None):

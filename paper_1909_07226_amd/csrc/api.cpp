@@ -556,16 +556,7 @@ struct GridScratch {
   float2 *subgrids = nullptr;
 };
 
-static int alloc_grid_scratch(int64_t slots, int64_t nsub, int L, hipStream_t s, GridScratch &g) {
-  const size_t part_bytes = size_t(slots) * 4 * idg::kAdderTile * idg::kAdderTile * sizeof(float2);
-  const size_t sub_bytes = size_t(nsub) * 4 * size_t(L) * L * sizeof(float2);
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&g.base), 256 + part_bytes + sub_bytes, s),
-          "scratch allocation");
-  g.counter = reinterpret_cast<int32_t *>(g.base);
-  g.partials = reinterpret_cast<float2 *>(g.base + 256);
-  g.subgrids = reinterpret_cast<float2 *>(g.base + 256 + part_bytes);
-  return IDG_OK;
-}
+
 
 static bool degrid_wide(const idg_plan_s *plan) {
   return plan->tuning.degrid_shape == IDG_DEGRID_WIDE && !(plan->host.params.flags & IDG_PHASE_FP32);
@@ -580,21 +571,34 @@ static int persistent_blocks(const idg_plan_s *plan, const DevPlan *dp, bool deg
   return std::max(1, per_cu * dp->nr_cus);
 }
 
-int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
-             const idg_cf32 *aterms_d, const float *taper_d, idg_cf32 *grid_d, void *stream) {
-  if (!plan) return fail(IDG_EINVAL, "idg_grid: plan is NULL");
-  if (plan->host.subgrids.empty()) return IDG_OK;
-  if (!uvw_d || !freqs_d || !vis_d || !aterms_d || !taper_d || !grid_d)
-    return fail(IDG_EINVAL, "idg_grid: NULL device pointer");
-  DevPlan *dp = nullptr;
-  int rc = device_plan(plan, &dp);
-  if (rc != IDG_OK) return rc;
+// Bytes of one idg_grid call's scratch: the queue counter, the partial tiles of split adder lists and the
+// transformed subgrids of one batch.
+static size_t grid_scratch_bytes(const DevPlan *dp, int64_t nsub, int L) {
+  return 256 + size_t(dp->max_slots) * 4 * idg::kAdderTile * idg::kAdderTile * sizeof(float2) +
+         size_t(nsub) * 4 * size_t(L) * L * sizeof(float2);
+}
+
+static void carve_grid_scratch(char *base, int64_t slots, GridScratch &g) {
+  g.base = base;
+  g.counter = reinterpret_cast<int32_t *>(base);
+  g.partials = reinterpret_cast<float2 *>(base + 256);
+  g.subgrids = reinterpret_cast<float2 *>(base + 256 + size_t(slots) * 4 * idg::kAdderTile * idg::kAdderTile *
+                                                       sizeof(float2));
+}
+
+static int alloc_grid_scratch(const DevPlan *dp, int64_t nsub, int L, hipStream_t s, GridScratch &g) {
+  char *base = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&base), grid_scratch_bytes(dp, nsub, L), s), "scratch allocation");
+  carve_grid_scratch(base, dp->max_slots, g);
+  return IDG_OK;
+}
+
+// The gridder and adder launches of idg_grid, batch by batch, with scratch g.
+static hipError_t grid_launches(idg_plan_t plan, const DevPlan *dp, const double *uvw_d, const double *freqs_d,
+                                const idg_cf32 *vis_d, const idg_cf32 *aterms_d, const float *taper_d,
+                                idg_cf32 *grid_d, const GridScratch &g, hipStream_t s) {
   const idg_params &p = plan->host.params;
   const int L = p.subgrid_size;
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t nb = std::min<int64_t>(dp->batch_size, int64_t(plan->host.subgrids.size()));
-  GridScratch g;
-  if ((rc = alloc_grid_scratch(dp->max_slots, nb, L, s, g)) != IDG_OK) return rc;
   const bool persistent = plan->tuning.grid_form == IDG_FORM_PERSISTENT;
   const int nblocks = persistent ? persistent_blocks(plan, dp, false) : 0;
   idg::KernelArgs a;
@@ -637,9 +641,66 @@ int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const 
     }
     if (err != hipSuccess) break;
   }
+  return err;
+}
+
+int idg_grid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
+             const idg_cf32 *aterms_d, const float *taper_d, idg_cf32 *grid_d, void *stream) {
+  if (!plan) return fail(IDG_EINVAL, "idg_grid: plan is NULL");
+  if (plan->host.subgrids.empty()) return IDG_OK;
+  if (!uvw_d || !freqs_d || !vis_d || !aterms_d || !taper_d || !grid_d)
+    return fail(IDG_EINVAL, "idg_grid: NULL device pointer");
+  DevPlan *dp = nullptr;
+  int rc = device_plan(plan, &dp);
+  if (rc != IDG_OK) return rc;
+  const int L = plan->host.params.subgrid_size;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t nb = std::min<int64_t>(dp->batch_size, int64_t(plan->host.subgrids.size()));
+  GridScratch g;
+  if ((rc = alloc_grid_scratch(dp, nb, L, s, g)) != IDG_OK) return rc;
+  const hipError_t err = grid_launches(plan, dp, uvw_d, freqs_d, vis_d, aterms_d, taper_d, grid_d, g, s);
   hipError_t ef = hipFreeAsync(g.base, s);
   if (err != hipSuccess) return hip_fail(err, "idg_grid: launch");
   HIP_TRY(ef, "idg_grid: scratch release");
+  return IDG_OK;
+}
+
+// The plan's device metadata on the current device, without uploading it.
+static int resident_device_plan(idg_plan_t plan, const char *fn, DevPlan **out) {
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+  std::lock_guard<std::mutex> lock(plan->mu);
+  auto it = plan->dev.find(device);
+  if (it == plan->dev.end())
+    return fail(IDG_ESTATE, "%s: the plan has no device copy on device %d (an idg_grid, idg_degrid or "
+                "idg_grid_subgrids call with this plan on this device makes one)", fn, device);
+  *out = it->second.get();
+  return IDG_OK;
+}
+
+int idg_grid_noalloc(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
+                     const idg_cf32 *aterms_d, const float *taper_d, idg_cf32 *grid_d, void *stream) {
+  if (!plan) return fail(IDG_EINVAL, "idg_grid_noalloc: plan is NULL");
+  if (plan->host.subgrids.empty()) return IDG_OK;
+  if (!uvw_d || !freqs_d || !vis_d || !aterms_d || !taper_d || !grid_d)
+    return fail(IDG_EINVAL, "idg_grid_noalloc: NULL device pointer");
+  DevPlan *dp = nullptr;
+  int rc = resident_device_plan(plan, "idg_grid_noalloc", &dp);
+  if (rc != IDG_OK) return rc;
+  const int L = plan->host.params.subgrid_size;
+  const int64_t nb = std::min<int64_t>(dp->batch_size, int64_t(plan->host.subgrids.size()));
+  const size_t need = grid_scratch_bytes(dp, nb, L);
+  if (need > idg::kNoAllocScratchBytes)
+    return fail(IDG_ERANGE, "idg_grid_noalloc: the plan needs %zu bytes of scratch per call (batches of %lld "
+                "subgrids), above the fixed %zu; plan with a smaller scratch_bytes", need, (long long)nb,
+                idg::kNoAllocScratchBytes);
+  void *base = nullptr;
+  HIP_TRY(idg::noalloc_scratch(&base), "idg_grid_noalloc: scratch address");
+  GridScratch g;
+  carve_grid_scratch(static_cast<char *>(base), dp->max_slots, g);
+  const hipError_t err = grid_launches(plan, dp, uvw_d, freqs_d, vis_d, aterms_d, taper_d, grid_d, g,
+                                       static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "idg_grid_noalloc: launch");
   return IDG_OK;
 }
 

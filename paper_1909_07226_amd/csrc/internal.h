@@ -96,6 +96,11 @@ hipError_t launch_subgrid_fft(int L, float2 *data, int64_t count, int direction,
                               hipStream_t s);
 hipError_t launch_zero_samples(const int64_t *ids, int64_t n, float2 *vis, hipStream_t s);
 
+// Device scratch of idg_grid_noalloc (kernels.hip): kNoAllocScratchBytes on the current device; the address
+// is looked up once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(IDG_NOALLOC_SCRATCH_BYTES);
+hipError_t noalloc_scratch(void **out);
+
 // master grid <-> image (image.hip)
 bool image_size_supported(int N);
 hipError_t launch_image_twiddles(float2 *tw, int N, hipStream_t s);

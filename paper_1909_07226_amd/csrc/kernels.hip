@@ -19,6 +19,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <atomic>
 
 namespace idg {
 
@@ -1302,6 +1303,33 @@ __global__ void zero_samples_kernel(const int64_t *ids, int64_t n, float2 *vis) 
     o[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     o[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of idg_grid_noalloc: a fixed device array, one per GPU that loads the
+// library, held until the process ends.  Host code never passes `scratch`
+// itself to a kernel (on the host the name is a stand-in, not a device
+// address): noalloc_scratch() looks up the array's device address once per
+// device with hipGetSymbolAddress and returns that.
+
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void **out) {
+  constexpr int kMaxDevices = 64;
+  static std::atomic<void *> addr[kMaxDevices];  // zero-initialised: not looked up yet
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  void *p = addr[dev].load(std::memory_order_acquire);
+  if (!p) {
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev].store(p, std::memory_order_release);
+  }
+  *out = p;
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

@@ -203,3 +203,20 @@ def test_image_steps_validate_before_any_device_call():
         assert fn(a, 256, None, None, vp(0x10000000 + 4096), None) == -1   # overlapping buffers
         L.idg_last_error.restype = ctypes.c_char_p
         assert b"overlap" in L.idg_last_error()
+
+
+def test_grid_noalloc_validates_before_any_device_call():
+    # NULL plan or NULL device pointers are refused on the host; fake addresses are never dereferenced
+    L = ctypes.CDLL(idg.LIB_PATH)
+    vp = ctypes.c_void_p
+    L.idg_grid_noalloc.argtypes = [vp] * 8
+    L.idg_grid_noalloc.restype = ctypes.c_int
+    f = vp(0x10000000)
+    assert L.idg_grid_noalloc(None, f, f, f, f, f, f, None) == -1
+    wl = random_track_workload(seed=3, nbl=2, nt=10, nch=2)
+    p = idg.Plan.from_workload(wl)
+    assert p.nr_subgrids > 0
+    assert L.idg_grid_noalloc(p.handle, f, None, f, f, f, f, None) == -1
+    L.idg_last_error.restype = ctypes.c_char_p
+    assert b"NULL" in L.idg_last_error()
+    assert idg.NOALLOC_SCRATCH_BYTES == 128 << 20
