@@ -170,14 +170,23 @@ int idg_plan_export(idg_plan_t plan, int64_t *subgrids, int32_t *samples);
  *                  per visibility, more registers; pays for large subgrids.
  *                  Results agree to float32 summation order.  Ignored with
  *                  IDG_PHASE_FP32;
+ *   sum_path       IDG_SUM_AUTO: subgrids of 32 x 32 whose w-term allows it run
+ *                  the separable form of the subgrid sum on the matrix cores
+ *                  (see idg_grid), the others the direct sum; IDG_SUM_DIRECT:
+ *                  every subgrid runs the direct sum.  Results agree to float32
+ *                  level (the separable form's operands carry 22 significant
+ *                  bits and its cross-term expansion is truncated below 1e-6);
  *   reserved       must be 0.
  * idg_plan_set_tuning validates (IDG_EINVAL) and stores the knobs; call it
  * only when no work queued with the plan is pending.  New plans start with
- * all fields 0 (plain forms, default chunk, standard degridder). */
+ * all fields 0 (plain forms, default chunk, standard degridder, automatic
+ * sum path). */
 #define IDG_FORM_PLAIN 0
 #define IDG_FORM_PERSISTENT 1
 #define IDG_DEGRID_STANDARD 0
 #define IDG_DEGRID_WIDE 1
+#define IDG_SUM_AUTO 0
+#define IDG_SUM_DIRECT 1
 typedef struct {
   int32_t grid_form;
   int32_t degrid_form;
@@ -185,7 +194,8 @@ typedef struct {
   int32_t degrid_blocks_per_cu;
   int32_t adder_chunk;
   int32_t degrid_shape;
-  int32_t reserved[2];
+  int32_t sum_path;
+  int32_t reserved;
 } idg_tuning;
 int idg_plan_set_tuning(idg_plan_t plan, const idg_tuning *tuning);
 int idg_plan_get_tuning(idg_plan_t plan, idg_tuning *tuning);
@@ -207,7 +217,14 @@ void idg_plan_destroy(idg_plan_t plan);
  * phasors of consecutive channels of one timestep are advanced by one complex
  * multiplication with a per-run step phasor (runs of at most 16 channels)
  * instead of a sin/cos per sample; the result agrees with the per-sample
- * evaluation to float32 rounding.  Device scratch of at most
+ * evaluation to float32 rounding.  Subgrids of 32 x 32 may instead run the
+ * separable form (tuning sum_path): with n' = a(l) + a(m) + c(l, m),
+ * a(x) = sqrt(1 - x^2) - 1, the phasor is U(l) V(m) exp(2 pi i dw c), the
+ * last factor expanded to the order (at most 2) that keeps its truncation
+ * below 1e-6 given the subgrid's largest |w - w_0p| (the plan computes it in
+ * float64); each order is a dense (32 x K)(K x 32) product per polarisation,
+ * on the matrix cores with fp16 high/low operand parts.  Subgrids whose
+ * w-term needs a higher order run the direct sum.  Device scratch of at most
  * params.scratch_bytes is allocated stream-ordered for the call.
  *
  *   uvw_d    float64 [nr_baselines][nr_timesteps][3]     freqs_d  float64 [nr_channels]

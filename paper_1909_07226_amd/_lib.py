@@ -28,6 +28,7 @@ EXPORTED = ("idg_plan", "idg_plan_stats", "idg_plan_export", "idg_plan_destroy",
 NOALLOC_SCRATCH_BYTES = 128 << 20          # IDG_NOALLOC_SCRATCH_BYTES
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 DEGRID_STANDARD, DEGRID_WIDE = 0, 1
+SUM_AUTO, SUM_DIRECT = 0, 1
 STAGES = ("gridder", "adder", "degridder", "zero")
 
 
@@ -42,13 +43,16 @@ class Params(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("grid_form", ctypes.c_int32), ("degrid_form", ctypes.c_int32),
                 ("grid_blocks_per_cu", ctypes.c_int32), ("degrid_blocks_per_cu", ctypes.c_int32),
-                ("adder_chunk", ctypes.c_int32), ("degrid_shape", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("adder_chunk", ctypes.c_int32), ("degrid_shape", ctypes.c_int32), ("sum_path", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _FORMS = {"plain": FORM_PLAIN, "persistent": FORM_PERSISTENT}
 _FORM_NAMES = {v: k for k, v in _FORMS.items()}
 _SHAPES = {"standard": DEGRID_STANDARD, "wide": DEGRID_WIDE}
 _SHAPE_NAMES = {v: k for k, v in _SHAPES.items()}
+_SUMS = {"auto": SUM_AUTO, "direct": SUM_DIRECT}
+_SUM_NAMES = {v: k for k, v in _SUMS.items()}
 
 
 class IDGError(RuntimeError):
@@ -206,10 +210,11 @@ class Plan:
         return [(lo + j) * self.params.w_step for j in range(n)]
 
     def set_tuning(self, form=None, blocks_per_cu=None, adder_chunk=None, grid_form=None, degrid_form=None,
-                   grid_blocks_per_cu=None, degrid_blocks_per_cu=None, degrid_shape=None):
+                   grid_blocks_per_cu=None, degrid_blocks_per_cu=None, degrid_shape=None, sum_path=None):
         """Scheduling knobs (idg_plan_set_tuning).  ``form`` / ``blocks_per_cu`` set both directions;
-        the grid_/degrid_ arguments set one; ``degrid_shape`` is "standard" or "wide".  Unspecified
-        knobs keep their value."""
+        the grid_/degrid_ arguments set one; ``degrid_shape`` is "standard" or "wide"; ``sum_path`` is
+        "auto" (separable form on the matrix cores where it applies) or "direct".  Unspecified knobs
+        keep their value."""
         cur = self.get_tuning()
         gf = grid_form if grid_form is not None else (form if form is not None else cur["grid_form"])
         df = degrid_form if degrid_form is not None else (form if form is not None else cur["degrid_form"])
@@ -218,8 +223,10 @@ class Plan:
         db = degrid_blocks_per_cu if degrid_blocks_per_cu is not None else (
             blocks_per_cu if blocks_per_cu is not None else cur["degrid_blocks_per_cu"])
         ds = cur["degrid_shape"] if degrid_shape is None else degrid_shape
+        sp = cur["sum_path"] if sum_path is None else sum_path
         t = Tuning(_FORMS.get(gf, gf), _FORMS.get(df, df), int(gb), int(db),
-                   cur["adder_chunk"] if adder_chunk is None else int(adder_chunk), _SHAPES.get(ds, ds))
+                   cur["adder_chunk"] if adder_chunk is None else int(adder_chunk), _SHAPES.get(ds, ds),
+                   _SUMS.get(sp, sp))
         check(lib().idg_plan_set_tuning(self._handle, ctypes.byref(t)))
 
     def get_tuning(self):
@@ -228,7 +235,8 @@ class Plan:
         return dict(grid_form=_FORM_NAMES.get(t.grid_form, t.grid_form),
                     degrid_form=_FORM_NAMES.get(t.degrid_form, t.degrid_form),
                     grid_blocks_per_cu=t.grid_blocks_per_cu, degrid_blocks_per_cu=t.degrid_blocks_per_cu,
-                    adder_chunk=t.adder_chunk, degrid_shape=_SHAPE_NAMES.get(t.degrid_shape, t.degrid_shape))
+                    adder_chunk=t.adder_chunk, degrid_shape=_SHAPE_NAMES.get(t.degrid_shape, t.degrid_shape),
+                    sum_path=_SUM_NAMES.get(t.sum_path, t.sum_path))
 
     def export(self):
         """(subgrids int64 [P, 13] with SUBGRID_FIELDS columns, samples int32 [K, 2] of (t, c))."""

@@ -36,7 +36,7 @@ def plan_key(plan):
     mean_k = st["nr_gridded"] / n
     dev = torch.cuda.get_device_properties(torch.cuda.current_device())
     arch = getattr(dev, "gcnArchName", dev.name)
-    return (f"v2|{arch}|L{plan.subgrid_size}|N{plan.grid_size}|P2^{int(np.log2(n))}"
+    return (f"v3|{arch}|L{plan.subgrid_size}|N{plan.grid_size}|P2^{int(np.log2(n))}"
             f"|K2^{int(np.log2(max(1.0, mean_k)))}")
 
 

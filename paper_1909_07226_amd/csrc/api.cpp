@@ -46,7 +46,8 @@ constexpr int64_t kDefaultScratch = int64_t(2) << 30;
 // Device-resident plan metadata on one device.
 struct Batch {
   int64_t first = 0, count = 0;      // plan subgrids [first, first + count)
-  int64_t order_off = 0;             // gridder work list (local indices, costliest first)
+  int64_t order_off = 0;             // gridder work list (local indices, costliest first): the subgrids of
+  int64_t n_sep = 0;                 // the separable form first (n_sep of them), then those of the direct sum
   int64_t item_off = 0, nitems = 0;  // adder items
   int64_t combine_off = 0, ncombine = 0;
   int64_t nslots = 0;                // partial tiles of this batch
@@ -60,17 +61,21 @@ struct DevPlan {
   int64_t *unplanned = nullptr;
   float4 *lmn = nullptr;
   float2 *twiddle = nullptr;
+  float2 *sep = nullptr;   // separable form: (x_q, a_q)
+  float *cross = nullptr;  // separable form: c_ij
   int32_t *grid_order = nullptr, *degrid_order = nullptr, *contrib = nullptr;
   idg::AdderItem *items = nullptr;
   idg::CombineItem *combine = nullptr;
   std::vector<Batch> batches;
   int64_t batch_size = 0, max_slots = 0;
-  int64_t degrid_n_large = 0;  // leading entries of degrid_order above the small-subgrid threshold
+  int64_t degrid_n_sep = 0;    // leading entries of degrid_order in the separable form
+  int64_t degrid_n_large = 0;  // then the entries above the small-subgrid threshold
 
   ~DevPlan() {
     int cur = -1;
     if (hipGetDevice(&cur) == hipSuccess && cur != device) (void)hipSetDevice(device);
-    void *ptrs[] = {subgrids, samples, unplanned, lmn, twiddle, grid_order, degrid_order, contrib, items, combine};
+    void *ptrs[] = {subgrids, samples, unplanned, lmn, twiddle, sep, cross, grid_order, degrid_order, contrib, items,
+                    combine};
     for (void *p : ptrs)
       if (p) (void)hipFree(p);
     if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
@@ -212,6 +217,7 @@ int upload(T **dst, const T *src, size_t n, const char *what) {
 
 struct idg_plan_s {
   idg::HostPlan host;
+  std::vector<double> wmax;  // per subgrid: largest |w - w_0p| of its samples, wavelengths (float64)
   idg_tuning tuning{};
   std::mutex mu;
   std::map<int, std::unique_ptr<DevPlan>> dev;
@@ -223,6 +229,41 @@ int64_t batch_size_of(const idg_params &p) {
   const int64_t per = int64_t(4) * p.subgrid_size * p.subgrid_size * int64_t(sizeof(idg_cf32));
   const int64_t budget = p.scratch_bytes > 0 ? p.scratch_bytes : kDefaultScratch;
   return std::max<int64_t>(1, std::min<int64_t>(budget / per, int64_t(1) << 30));
+}
+
+// Separable form: x_q = (q - L/2) S / L, a_q = sqrt(1 - x_q^2) - 1 and c_ij = n'_ij - a_i - a_j, so that
+// n'_ij = a_i + a_j + c_ij exactly in float64.  Returns max |c_ij|.
+double separable_tables(int L, double S, std::vector<float2> &sep, std::vector<float> &cross) {
+  auto nprime = [](double r2) { return -r2 / (1.0 + std::sqrt(1.0 - r2)); };  // sqrt(1 - r2) - 1, no cancellation
+  std::vector<double> x(static_cast<size_t>(L)), av(static_cast<size_t>(L));
+  sep.resize(size_t(L));
+  for (int q = 0; q < L; ++q) {
+    x[size_t(q)] = (q - L / 2) * (S / L);
+    av[size_t(q)] = nprime(x[size_t(q)] * x[size_t(q)]);
+    sep[size_t(q)] = make_float2(float(x[size_t(q)]), float(av[size_t(q)]));
+  }
+  cross.resize(size_t(L) * L);
+  double cmax = 0.0;
+  for (int j = 0; j < L; ++j)
+    for (int i = 0; i < L; ++i) {
+      const double c = nprime(x[size_t(i)] * x[size_t(i)] + x[size_t(j)] * x[size_t(j)]) - av[size_t(i)] - av[size_t(j)];
+      cross[size_t(j) * L + i] = float(c);
+      cmax = std::max(cmax, std::fabs(c));
+    }
+  return cmax;
+}
+
+// Expansion order of the separable form's cross term for a subgrid whose largest |w - w_0p| is wmax:
+// the smallest N with (2 pi wmax cmax)^(N+1) / (N+1)! <= 1e-6, or -1 when N would exceed max_order.
+int separable_order(double wmax, double cmax, int max_order) {
+  const double theta = 2.0 * M_PI * wmax * cmax;
+  double term = theta, fact = 1.0;
+  for (int n = 0; n <= max_order; ++n) {
+    fact *= double(n + 1);
+    if (term / fact <= 1e-6) return n;
+    term *= theta;
+  }
+  return -1;
 }
 
 void lmn_table(int L, double S, std::vector<float4> &lmn, std::vector<float2> &tw) {
@@ -271,11 +312,26 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
     d.vis_offset = r.vis_offset;
     d.w0 = double(r.wlayer) * p.w_step;
     d.layer = r.wlayer - h.wlayer_min;
-    d.pad = 0;
+    d.order = -1;
+    d.wexp = 0;
   }
   std::vector<float4> lmn;
   std::vector<float2> tw;
   lmn_table(L, p.image_size, lmn, tw);
+  std::vector<float2> sep;
+  std::vector<float> cross;
+  const double cmax = separable_tables(L, p.image_size, sep, cross);
+  // separable form: the expansion order and the power-of-two bound of |w - w_0p| per subgrid
+  const bool sep_on = idg::separable_supported(L) && !(p.flags & IDG_PHASE_FP32) &&
+                      plan->tuning.sum_path == IDG_SUM_AUTO;
+  if (sep_on)
+    for (size_t i = 0; i < subs.size(); ++i) {
+      const double wm = plan->wmax[i];
+      int e = 0;
+      if (wm > 0.0) (void)std::frexp(wm, &e);  // wm < 2^e
+      subs[i].order = int16_t(separable_order(wm, cmax, idg::separable_max_order()));
+      subs[i].wexp = int16_t(std::max(-120, std::min(120, e)));
+    }
   int rc;
   if ((rc = upload(&dp->subgrids, subs.data(), subs.size(), "plan upload (subgrids)")) != IDG_OK) return rc;
   if ((rc = upload(&dp->samples, h.samples.data(), h.samples.size(), "plan upload (samples)")) != IDG_OK) return rc;
@@ -283,6 +339,8 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
     return rc;
   if ((rc = upload(&dp->lmn, lmn.data(), lmn.size(), "plan upload (lmn)")) != IDG_OK) return rc;
   if ((rc = upload(&dp->twiddle, tw.data(), tw.size(), "plan upload (twiddle)")) != IDG_OK) return rc;
+  if ((rc = upload(&dp->sep, sep.data(), sep.size(), "plan upload (separable tables)")) != IDG_OK) return rc;
+  if ((rc = upload(&dp->cross, cross.data(), cross.size(), "plan upload (separable tables)")) != IDG_OK) return rc;
 
   // cost-sorted work lists: gridder per batch (local indices), degridder over the plan
   const int64_t P = int64_t(h.subgrids.size());
@@ -294,8 +352,15 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
   std::vector<int32_t> degrid_order(static_cast<size_t>(P));
   for (int64_t i = 0; i < P; ++i) degrid_order[size_t(i)] = int32_t(i);
   by_cost(degrid_order, 0);
-  for (int64_t i = 0; i < P; ++i)
-    if (h.subgrids[size_t(degrid_order[size_t(i)])].nvis > idg::degrid_small_threshold()) dp->degrid_n_large = i + 1;
+  std::stable_partition(degrid_order.begin(), degrid_order.end(),
+                        [&](int32_t x) { return subs[size_t(x)].order >= 0; });
+  for (int64_t i = 0; i < P; ++i) {
+    const idg::DevSubgrid &r = subs[size_t(degrid_order[size_t(i)])];
+    if (r.order >= 0)
+      dp->degrid_n_sep++;
+    else if (r.nvis > idg::degrid_small_threshold())
+      dp->degrid_n_large++;
+  }
 
   // per scratch batch: gridder order and adder items over tile lists
   dp->batch_size = batch_size_of(p);
@@ -310,6 +375,9 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
     std::vector<int32_t> ord(static_cast<size_t>(b.count));
     for (int64_t i = 0; i < b.count; ++i) ord[size_t(i)] = int32_t(i);
     by_cost(ord, f);
+    // the separable-form subgrids first (each part still costliest first)
+    std::stable_partition(ord.begin(), ord.end(), [&](int32_t x) { return subs[size_t(f + x)].order >= 0; });
+    for (int32_t x : ord) b.n_sep += subs[size_t(f + x)].order >= 0 ? 1 : 0;
     b.order_off = int64_t(grid_order.size());
     grid_order.insert(grid_order.end(), ord.begin(), ord.end());
     TileLists tl;
@@ -447,6 +515,25 @@ int idg_plan(const idg_params *params, const int32_t *baselines, const double *u
     delete plan;
     return fail(IDG_EINVAL, "idg_plan: W-layers x grid tiles exceed 2^31");
   }
+  try {  // per subgrid the largest |w - w_0p| of its samples (separable form), in float64
+    const idg::HostPlan &h = plan->host;
+    plan->wmax.assign(h.subgrids.size(), 0.0);
+    for (size_t i = 0; i < h.subgrids.size(); ++i) {
+      const idg::SubgridRec &r = h.subgrids[i];
+      const double w0 = double(r.wlayer) * p.w_step;
+      double wm = 0.0;
+      for (int64_t k = 0; k < r.nvis; ++k) {
+        const uint32_t pk = h.samples[size_t(r.vis_offset + k)];
+        const int t = r.t0 + int(pk >> 16), c = r.c0 + int(pk & 0xffffu);
+        const double w = uvw[(int64_t(r.bl) * p.nr_timesteps + t) * 3 + 2] * (freqs[c] / idg::kSpeedOfLight);
+        wm = std::max(wm, std::fabs(w - w0));
+      }
+      plan->wmax[i] = wm;
+    }
+  } catch (const std::bad_alloc &) {
+    delete plan;
+    return fail(IDG_ENOMEM, "idg_plan: out of host memory");
+  }
   if ((p.flags & IDG_STRICT) && plan->host.nr_dropped > 0) {
     const long long nd = (long long)plan->host.nr_dropped;
     delete plan;
@@ -505,6 +592,8 @@ static void fill_kernel_args(const idg_plan_s *plan, const DevPlan *dp, idg::Ker
   a.samples = dp->samples;
   a.lmn = dp->lmn;
   a.twiddle = dp->twiddle;
+  a.sep = dp->sep;
+  a.cross = dp->cross;
   a.nr_timesteps = p.nr_timesteps;
   a.nr_channels = p.nr_channels;
   a.grid_size = p.grid_size;
@@ -543,7 +632,7 @@ int idg_grid_subgrids(idg_plan_t plan, const double *uvw_d, const double *freqs_
     a.first = first + f;
     a.count = int32_t(std::min<int64_t>(count - f, int64_t(1) << 30));
     a.subgrids_out = reinterpret_cast<float2 *>(out_d) + f * 4 * L * L;
-    HIP_TRY(idg::launch_gridder(L, a, s), "gridder launch");
+    HIP_TRY(idg::launch_gridder(L, a, nullptr, s), "gridder launch");
   }
   return IDG_OK;
 }
@@ -612,13 +701,24 @@ static hipError_t grid_launches(idg_plan_t plan, const DevPlan *dp, const double
   a.stage = 1;
   a.pieces = 1;  // the adder reads each tile's piece of a subgrid as one block
   hipError_t err = hipSuccess;
+  const int nblocks_sep = persistent ? std::max(1, (plan->tuning.grid_blocks_per_cu > 0 ? plan->tuning.grid_blocks_per_cu
+                                                                                      : idg::mfma_gridder_blocks_per_cu(L)) *
+                                                       dp->nr_cus)
+                                     : 0;
   for (const Batch &b : dp->batches) {
     a.first = b.first;
-    a.count = int32_t(b.count);
+    const int32_t *ord = dp->grid_order + b.order_off;
     {
+      // separable form (matrix cores) over ord[0 .. n_sep), direct sum over the rest; two queue counters
       StageTimer tm(IDG_STAGE_GRIDDER, s);
-      err = persistent ? idg::launch_gridder_persistent(L, a, dp->grid_order + b.order_off, g.counter, nblocks, s)
-                       : idg::launch_gridder(L, a, s);
+      a.count = int32_t(b.n_sep);
+      err = persistent ? idg::launch_gridder_mfma_persistent(L, a, ord, g.counter, nblocks_sep, s)
+                       : idg::launch_gridder_mfma(L, a, ord, s);
+      if (err == hipSuccess) {
+        a.count = int32_t(b.count - b.n_sep);
+        err = persistent ? idg::launch_gridder_persistent(L, a, ord + b.n_sep, g.counter + 1, nblocks, s)
+                         : idg::launch_gridder(L, a, ord + b.n_sep, s);
+      }
     }
     if (err != hipSuccess) break;
     idg::AdderArgs ad{};
@@ -734,14 +834,16 @@ int idg_degrid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, cons
   a.first = 0;
   a.count = int32_t(P);
   if (plan->tuning.degrid_form == IDG_FORM_PERSISTENT) {
-    int32_t *counter = nullptr;  // two queue counters: subgrids above and below the small-subgrid threshold
+    int32_t *counter = nullptr;  // queue counters: large and small subgrids of the direct sum, separable form
     HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&counter), 256, s), "idg_degrid: queue counter");
     hipError_t err;
     {
       StageTimer tm(IDG_STAGE_DEGRIDDER, s);
-      err = idg::launch_degridder_persistent(L, a, degrid_wide(plan), dp->degrid_order, dp->degrid_n_large, counter,
-                                             persistent_blocks(plan, dp, true), persistent_blocks(plan, dp, true, true),
-                                             s);
+      const int want = plan->tuning.degrid_blocks_per_cu;
+      const int nb_sep = std::max(1, (want > 0 ? want : idg::mfma_degridder_blocks_per_cu(L)) * dp->nr_cus);
+      err = idg::launch_degridder_persistent(L, a, degrid_wide(plan), dp->degrid_order, dp->degrid_n_sep,
+                                             dp->degrid_n_large, counter, nb_sep, persistent_blocks(plan, dp, true),
+                                             persistent_blocks(plan, dp, true, true), s);
     }
     hipError_t ef = hipFreeAsync(counter, s);
     if (err != hipSuccess) return hip_fail(err, "idg_degrid: launch");
@@ -749,7 +851,7 @@ int idg_degrid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, cons
     return IDG_OK;
   }
   StageTimer tm(IDG_STAGE_DEGRIDDER, s);
-  HIP_TRY(idg::launch_degridder(L, a, degrid_wide(plan), dp->degrid_order, dp->degrid_n_large, s),
+  HIP_TRY(idg::launch_degridder(L, a, degrid_wide(plan), dp->degrid_order, dp->degrid_n_sep, dp->degrid_n_large, s),
           "idg_degrid: launch");
   return IDG_OK;
 }
@@ -764,11 +866,14 @@ int idg_plan_set_tuning(idg_plan_t plan, const idg_tuning *t) {
   if (t->adder_chunk < 0) return fail(IDG_EINVAL, "idg_plan_set_tuning: adder_chunk must be >= 0");
   if (t->degrid_shape != IDG_DEGRID_STANDARD && t->degrid_shape != IDG_DEGRID_WIDE)
     return fail(IDG_EINVAL, "idg_plan_set_tuning: unknown degrid_shape %d", t->degrid_shape);
-  if (t->reserved[0] || t->reserved[1]) return fail(IDG_EINVAL, "idg_plan_set_tuning: reserved must be 0");
+  if (t->sum_path != IDG_SUM_AUTO && t->sum_path != IDG_SUM_DIRECT)
+    return fail(IDG_EINVAL, "idg_plan_set_tuning: unknown sum_path %d", t->sum_path);
+  if (t->reserved) return fail(IDG_EINVAL, "idg_plan_set_tuning: reserved must be 0");
   std::lock_guard<std::mutex> lock(plan->mu);
-  const bool rebuild = t->adder_chunk != plan->tuning.adder_chunk;
+  // adder items depend on the chunk length, the gridder work lists on the sum path
+  const bool rebuild = t->adder_chunk != plan->tuning.adder_chunk || t->sum_path != plan->tuning.sum_path;
   plan->tuning = *t;
-  if (rebuild) plan->dev.clear();  // adder items depend on the chunk length; rebuilt on next use
+  if (rebuild) plan->dev.clear();  // rebuilt on next use
   return IDG_OK;
 }
 

@@ -17,7 +17,8 @@ struct alignas(16) DevSubgrid {
   int64_t vis_offset;  // first packed sample of this subgrid
   double w0;           // w offset of the subgrid's W-layer, wavelengths (0 without layers)
   int32_t layer;       // index of that layer's [4][N][N] grid
-  int32_t pad;
+  int16_t order;       // separable form: expansion order of the cross term (-1: direct sum only)
+  int16_t wexp;        // separable form: |w - w0| <= 2^wexp over the subgrid's samples
 };
 static_assert(sizeof(DevSubgrid) == 64, "DevSubgrid layout");
 
@@ -33,6 +34,8 @@ struct KernelArgs {
   const float *taper;          // [L*L]
   const float4 *lmn;           // [L*L] (l, m, n', 0) float32 from float64
   const float2 *twiddle;       // [L] exp(-2 pi i k / L)
+  const float2 *sep;           // [L] (x_q, sqrt(1 - x_q^2) - 1), x_q = (q - L/2) S / L (separable form)
+  const float *cross;          // [L*L] n'_ij - a_i - a_j (separable form)
   const float2 *grid_in;       // degridder: [4][N][N]
   float2 *subgrids_out;        // gridder: [count][4][L*L]
   int64_t first;               // first plan subgrid of this launch
@@ -75,20 +78,31 @@ struct AdderArgs {
 
 bool supported_subgrid_size(int L);
 
-hipError_t launch_gridder(int L, const KernelArgs &a, hipStream_t s);
-// Degridder: `order` holds a.count global subgrid indices sorted by visibility count, costliest
-// first; its first n_large items have more than degrid_small_threshold() visibilities (they run the
-// visibility-per-lane kernel, the rest the pixel-per-lane kernel).
+// Gridder, direct sum on the VALU: a.count subgrids, local indices order[0 .. count) (order NULL: 0 .. count).
+hipError_t launch_gridder(int L, const KernelArgs &a, const int32_t *order, hipStream_t s);
+// Gridder, separable form on the matrix cores (L = 32 only; subgrids with 0 <= order <= separable_max_order()).
+int separable_max_order();
+bool separable_supported(int L);
+hipError_t launch_gridder_mfma(int L, const KernelArgs &a, const int32_t *order, hipStream_t s);
+hipError_t launch_gridder_mfma_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
+                                          int nblocks, hipStream_t s);
+// Degridder: `order` holds a.count global subgrid indices: the n_sep subgrids of the separable form first,
+// then the others sorted by visibility count, costliest first; the first n_large of those have more than
+// degrid_small_threshold() visibilities (they run the visibility-per-lane kernel, the rest the
+// pixel-per-lane kernel).
 int degrid_small_threshold();
-hipError_t launch_degridder(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_large,
-                            hipStream_t s);
+hipError_t launch_degridder(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_sep,
+                            int64_t n_large, hipStream_t s);
 // persistent forms: `order` holds a.count items; the gridder's *queue_head (one counter) and the
-// degridder's queue_head[0..1] (large and small subgrids) are zeroed by the launcher
+// degridder's queue_head[0..2] (large, small, separable) are zeroed by the launcher
 hipError_t launch_gridder_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
                                      int nblocks, hipStream_t s);
-hipError_t launch_degridder_persistent(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_large,
-                                       int32_t *queue_head, int nblocks_large, int nblocks_small, hipStream_t s);
+hipError_t launch_degridder_persistent(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_sep,
+                                       int64_t n_large, int32_t *queue_head, int nblocks_sep, int nblocks_large,
+                                       int nblocks_small, hipStream_t s);
 int persistent_blocks_per_cu(int L, bool degrid, bool wide, bool small);
+int mfma_gridder_blocks_per_cu(int L);
+int mfma_degridder_blocks_per_cu(int L);
 hipError_t launch_adder(int L, const AdderArgs &a, hipStream_t s);
 hipError_t launch_splitter(int L, const DevSubgrid *subgrids, int64_t first, int64_t count, const float2 *grid,
                            int grid_size, float2 *out, hipStream_t s);

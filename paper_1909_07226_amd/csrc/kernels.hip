@@ -421,6 +421,7 @@ struct GridderSmem {
   float4 raw[RAW / 16];  // staged samples (offsets, channel steps, visibilities), then the subgrid
   float2 tw[L];
   int next;              // work-queue item of the persistent form
+  unsigned ybits;        // separable form: largest |visibility component| of the subgrid (float bits)
 };
 
 // Per-thread pixel coordinates (PPT pixels tid + r NT).
@@ -450,6 +451,44 @@ __device__ __forceinline__ void grid_accumulate(float2 (&acc)[PPT][4], const flo
     cmac(acc[r][1], v01.z, v01.w, ph[r].x, ph[r].y);
     cmac(acc[r][2], v23.x, v23.y, ph[r].x, ph[r].y);
     cmac(acc[r][3], v23.z, v23.w, ph[r].x, ph[r].y);
+  }
+}
+
+// Gridder epilogue: this thread's pixels' sums acc (tid + r NT) -> A-terms x
+// taper per pixel -> LDS -> centred DFT (stage 1) -> the subgrid's slot of
+// a.subgrids_out.  Starts with s_sg free (all threads past their last read of
+// it); the caller synchronises before reusing shared memory.
+template <int L>
+__device__ __forceinline__ void grid_finish(const KernelArgs &a, const DevSubgrid &d, int local,
+                                            float2 (&acc)[L * L / Cfg<L>::NT][4], float2 *s_sg, const float2 *tw) {
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT;
+  const int tid = threadIdx.x;
+  const float2 *j1 = a.aterms + int64_t(d.a1) * NPIX * 4;
+  const float2 *j2 = a.aterms + int64_t(d.a2) * NPIX * 4;
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int pix = tid + r * NT;
+    float2 J1[4], J2[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      J1[e] = j1[pix * 4 + e];
+      J2[e] = j2[pix * 4 + e];
+    }
+    apply_aterms_grid(J1, J2, a.taper[pix], acc[r]);
+#pragma unroll
+    for (int pol = 0; pol < 4; ++pol) s_sg[SgLayout<L>::idx(pol, pix)] = acc[r][pol];
+  }
+  __syncthreads();
+  if (a.stage == 1) lds_centred_dft<L, NT, false>(s_sg, tw);
+
+  float2 *out = a.subgrids_out + int64_t(local) * 4 * NPIX;
+  const int ox = d.x0 % kAdderTile, oy = d.y0 % kAdderTile;
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    const int pix = tid + r * NT;
+    const int o = a.pieces ? piece_index<L>(pix / L, pix % L, ox, oy) : pix;
+#pragma unroll
+    for (int pol = 0; pol < 4; ++pol) out[pol * NPIX + o] = s_sg[SgLayout<L>::idx(pol, pix)];
   }
 }
 
@@ -562,43 +601,17 @@ __device__ __forceinline__ void grid_one(const KernelArgs &a, int local, Gridder
     __syncthreads();
   }
 
-  // A-terms x taper per pixel, into LDS for the transform
-  const float2 *j1 = a.aterms + int64_t(d.a1) * NPIX * 4;
-  const float2 *j2 = a.aterms + int64_t(d.a2) * NPIX * 4;
-#pragma unroll
-  for (int r = 0; r < PPT; ++r) {
-    const int pix = tid + r * NT;
-    float2 J1[4], J2[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      J1[e] = j1[pix * 4 + e];
-      J2[e] = j2[pix * 4 + e];
-    }
-    apply_aterms_grid(J1, J2, a.taper[pix], acc[r]);
-#pragma unroll
-    for (int pol = 0; pol < 4; ++pol) s_sg[SgLayout<L>::idx(pol, pix)] = acc[r][pol];
-  }
-  __syncthreads();
-  if (a.stage == 1) lds_centred_dft<L, NT, false>(s_sg, sm.tw);
-
-  float2 *out = a.subgrids_out + int64_t(local) * 4 * NPIX;
-  const int ox = d.x0 % kAdderTile, oy = d.y0 % kAdderTile;
-#pragma unroll
-  for (int r = 0; r < PPT; ++r) {
-    const int pix = tid + r * NT;
-    const int o = a.pieces ? piece_index<L>(pix / L, pix % L, ox, oy) : pix;
-#pragma unroll
-    for (int pol = 0; pol < 4; ++pol) out[pol * NPIX + o] = s_sg[SgLayout<L>::idx(pol, pix)];
-  }
+  grid_finish<L>(a, d, local, acc, s_sg, sm.tw);
 }
 
+// Plain form: one workgroup per subgrid, local index order[blockIdx.x] (or blockIdx.x without a list).
 template <int L, bool FP32_PHASE>
-__global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a) {
+__global__ void __launch_bounds__(Cfg<L>::NT) gridder_kernel(KernelArgs a, const int32_t *order) {
   __shared__ GridderSmem<L> sm;
   if (threadIdx.x < L) sm.tw[threadIdx.x] = a.twiddle[threadIdx.x];
   PixelCoords<L> pc;
   pc.load(a.lmn);
-  grid_one<L, FP32_PHASE>(a, blockIdx.x, sm, pc);
+  grid_one<L, FP32_PHASE>(a, order ? order[blockIdx.x] : int(blockIdx.x), sm, pc);
 }
 
 // Persistent form: items order[0 .. count-1] (local subgrid indices, costliest
@@ -630,6 +643,273 @@ gridder_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_hea
 }
 
 // ---------------------------------------------------------------------------
+// Separable form of the subgrid sum, on the matrix cores (L = 32).
+//
+// Pixel (j, i) of a subgrid sits at l = x_i, m = x_j.  Writing
+// n'_ij = a(x_i) + a(x_j) + c_ij with a(x) = sqrt(1 - x^2) - 1 (an exact split:
+// c_ij is whatever of n' is not a sum of a function of l and one of m, about
+// -l^2 m^2 / 4, at most about S^4 / 32), the phasor of sample k factors as
+//   E_k(i, j) = U_k(i) V_k(j) exp(2 pi i dw_k c_ij),
+//   U_k(i) = exp(2 pi i (du_k x_i + dw_k a_i)),  V_k(j) = exp(2 pi i (dv_k x_j + dw_k a_j)),
+// and the last factor is expanded to order N, which the plan chooses per
+// subgrid from its largest |dw| so that the truncation, below
+// (2 pi |dw| max|c|)^(N+1) / (N+1)!, stays under 1e-6:
+//   S[j][i] = sum_n (2 pi i c_ij)^n / n! G_n[j][i],  G_n[j][i] = sum_k V_k(j) dw_k^n Y_k U_k(i).
+// For each polarisation each G_n is a dense (32 x K)(K x 32) complex matrix
+// product: v_mfma_f32_32x32x16_f16 on operands split into fp16 high and low
+// parts (22 significant bits), accumulating hi*hi + hi*lo + lo*hi in float32.
+// The sines and cosines drop from one pair per (sample, pixel) to two pairs per
+// (sample, row or column).  Operands are scaled by powers of two (the largest
+// visibility component of the subgrid, the plan's largest |dw|) to stay inside
+// the fp16 range; the scales are undone exactly on the float32 sums.
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kSeparableMaxOrder = 1;  // expansion orders the matrix-core kernels carry
+
+// x = hi + lo, both fp16 (truncating conversions: x - hi is exact in float32)
+__device__ __forceinline__ void split_half8(const float (&x)[8], half8 &hi, half8 &lo) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const auto h = __builtin_amdgcn_cvt_pkrtz(x[2 * q], x[2 * q + 1]);
+    const auto r = __builtin_amdgcn_cvt_pkrtz(x[2 * q] - float(h[0]), x[2 * q + 1] - float(h[1]));
+    hi[2 * q] = h[0];
+    hi[2 * q + 1] = h[1];
+    lo[2 * q] = r[0];
+    lo[2 * q + 1] = r[1];
+  }
+}
+
+// d += (ah + al)(bh + bl) without the lo*lo term
+__device__ __forceinline__ floatx16 mfma_split(half8 ah, half8 al, half8 bh, half8 bl, floatx16 d) {
+  d = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, d, 0, 0, 0);
+  d = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, d, 0, 0, 0);
+  d = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, d, 0, 0, 0);
+  return d;
+}
+
+// Largest of v over the workgroup (v >= 0), through *slot (zeroed by the caller before a barrier).
+__device__ __forceinline__ void block_max_into(float v, unsigned *slot) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(v));
+}
+
+// Matrix-core operands of one block of 16 samples for one lane: A = V (row rc, samples kh .. kh + 7) as fp16
+// high/low parts of its real part, its imaginary part and minus its imaginary part; B = Y U for order 0 (high
+// and low parts) and dw Y U for order 1 (high parts: that term is scaled by |2 pi dw c| <= 1.5e-3, so fp16
+// rounding of it stays below 1e-6 of a phasor).
+struct SepOps {
+  half8 vrh, vrl, vih, vil, nvih, nvil;
+  half8 brh, brl, bih, bil;
+  half8 b1rh, b1ih;
+};
+
+// s_u, s_v, s_w: staged du, dv, dw; s_yr, s_yi: this polarisation's visibilities; samples kb + kh + (0..7).
+__device__ __forceinline__ void sep_operands(const float *s_u, const float *s_v, const float *s_w, const float *s_yr,
+                                             const float *s_yi, int k, float2 xa, float yinv, float winv,
+                                             bool order1, SepOps &o) {
+  float du[8], dv[8], dw[8], yr[8], yi[8];
+  *reinterpret_cast<float4 *>(du) = *reinterpret_cast<const float4 *>(s_u + k);
+  *reinterpret_cast<float4 *>(du + 4) = *reinterpret_cast<const float4 *>(s_u + k + 4);
+  *reinterpret_cast<float4 *>(dv) = *reinterpret_cast<const float4 *>(s_v + k);
+  *reinterpret_cast<float4 *>(dv + 4) = *reinterpret_cast<const float4 *>(s_v + k + 4);
+  *reinterpret_cast<float4 *>(dw) = *reinterpret_cast<const float4 *>(s_w + k);
+  *reinterpret_cast<float4 *>(dw + 4) = *reinterpret_cast<const float4 *>(s_w + k + 4);
+  *reinterpret_cast<float4 *>(yr) = *reinterpret_cast<const float4 *>(s_yr + k);
+  *reinterpret_cast<float4 *>(yr + 4) = *reinterpret_cast<const float4 *>(s_yr + k + 4);
+  *reinterpret_cast<float4 *>(yi) = *reinterpret_cast<const float4 *>(s_yi + k);
+  *reinterpret_cast<float4 *>(yi + 4) = *reinterpret_cast<const float4 *>(s_yi + k + 4);
+  float vr[8], vi[8], br[8], bi[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const float pv = __builtin_amdgcn_fractf(dv[s] * xa.x + dw[s] * xa.y);
+    const float pu = __builtin_amdgcn_fractf(du[s] * xa.x + dw[s] * xa.y);
+    vr[s] = __builtin_amdgcn_cosf(pv);
+    vi[s] = __builtin_amdgcn_sinf(pv);
+    const float ur = __builtin_amdgcn_cosf(pu), ui = __builtin_amdgcn_sinf(pu);
+    const float y0 = yr[s] * yinv, y1 = yi[s] * yinv;
+    br[s] = y0 * ur - y1 * ui;
+    bi[s] = y0 * ui + y1 * ur;
+  }
+  split_half8(vr, o.vrh, o.vrl);
+  split_half8(vi, o.vih, o.vil);
+  o.nvih = -o.vih;
+  o.nvil = -o.vil;
+  split_half8(br, o.brh, o.brl);
+  split_half8(bi, o.bih, o.bil);
+  if (order1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float w0 = dw[2 * q] * winv, w1 = dw[2 * q + 1] * winv;
+      const auto hr = __builtin_amdgcn_cvt_pkrtz(br[2 * q] * w0, br[2 * q + 1] * w1);
+      const auto hi = __builtin_amdgcn_cvt_pkrtz(bi[2 * q] * w0, bi[2 * q + 1] * w1);
+      o.b1rh[2 * q] = hr[0];
+      o.b1rh[2 * q + 1] = hr[1];
+      o.b1ih[2 * q] = hi[0];
+      o.b1ih[2 * q + 1] = hi[1];
+    }
+  }
+}
+
+// G_0 += V (Y U) with the split products; G_1 += V (dw Y U) with high parts (order 1)
+__device__ __forceinline__ void sep_mfma(const SepOps &o, bool order1, floatx16 (&gr)[2], floatx16 (&gi)[2]) {
+  // G_r += Vr Br - Vi Bi,  G_i += Vr Bi + Vi Br
+  gr[0] = mfma_split(o.vrh, o.vrl, o.brh, o.brl, gr[0]);
+  gi[0] = mfma_split(o.vrh, o.vrl, o.bih, o.bil, gi[0]);
+  gr[0] = mfma_split(o.nvih, o.nvil, o.bih, o.bil, gr[0]);
+  gi[0] = mfma_split(o.vih, o.vil, o.brh, o.brl, gi[0]);
+  if (order1) {
+    gr[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.vrh, o.b1rh, gr[1], 0, 0, 0);
+    gi[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.vrh, o.b1ih, gi[1], 0, 0, 0);
+    gr[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.nvih, o.b1ih, gr[1], 0, 0, 0);
+    gi[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(o.vih, o.b1rh, gi[1], 0, 0, 0);
+  }
+}
+
+// Grid plan subgrid a.first + local with the separable form (d.order = N in 0..1).  Four waves, wave w
+// accumulates polarisation w.  A, B and D of v_mfma_f32_32x32x16_f16: lane l holds A[l % 32][8 (l / 32) + s]
+// and B[8 (l / 32) + s][l % 32] (s = 0..7); D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] is element r of lane l.
+// The operands of the next block of samples are formed while the matrix cores work on the current one.
+template <int L>
+__device__ __forceinline__ void grid_one_mfma(const KernelArgs &a, int local, GridderSmem<L> &sm) {
+  static_assert(L == 32 && Cfg<L>::NT == 256, "the matrix-core gridder runs 32 x 32 subgrids on four waves");
+  static_assert(kSeparableMaxOrder == 1, "the matrix-core gridder carries orders 0 and 1");
+  constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT, CH = GridderSmem<L>::CH;
+  float *s_u = reinterpret_cast<float *>(sm.raw);  // [CH] du, then dv, dw, then [4][2][CH] visibilities
+  float *s_v = s_u + CH, *s_w = s_u + 2 * CH;
+  float *s_y = s_u + 3 * CH;
+  float2 *s_sg = reinterpret_cast<float2 *>(sm.raw);
+  const int tid = threadIdx.x, lane = tid & 63, pol = tid >> 6;
+  const DevSubgrid d = a.subgrids[a.first + local];
+  const int K = d.nvis;
+  const bool order1 = d.order >= 1;
+  const double S = a.image_size;
+  const double u0 = double(d.x0 + L / 2 - a.grid_size / 2) / S;
+  const double v0 = double(d.y0 + L / 2 - a.grid_size / 2) / S;
+  const uint32_t *smp = a.samples + d.vis_offset;
+  const float winv = ldexpf(1.0f, -int(d.wexp));
+  const int rc = lane & 31, kh = (lane >> 5) * 8;  // row (A) / column (B) of this lane, its first sample slot
+  const float2 xa = a.sep[rc];                      // (x, a(x)) of row / column rc
+  const float *s_yr = s_y + (2 * pol) * CH, *s_yi = s_y + (2 * pol + 1) * CH;
+  floatx16 gr[2], gi[2];
+#pragma unroll
+  for (int n = 0; n < 2; ++n)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) gr[n][e] = gi[n][e] = 0.0f;
+
+  // The fp16 operands carry the visibilities divided by 2^yexp >= their largest component so far; when a
+  // later staging round holds a larger one, the sums are rescaled by the (exact) power of two first.
+  int yexp = -126;
+  for (int k0 = 0; k0 < K; k0 += CH) {
+    const int nk = min(CH, K - k0), nkp = (nk + 15) & ~15;  // whole blocks of 16; the padding is zero
+    float ym = 0.0f;
+    if (tid == 0) sm.ybits = 0u;
+    if (tid < nkp) {
+      float du = 0.0f, dv = 0.0f, dw = 0.0f;
+      float4 p0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), p1 = p0;
+      if (tid < nk) {
+        const uint32_t pk = smp[k0 + tid];
+        const int t = d.t0 + int(pk >> 16), c = d.c0 + int(pk & 0xffffu);
+        const int64_t bt = int64_t(d.bl) * a.nr_timesteps + t;
+        const double *q = a.uvw + bt * 3;
+        const double sc = a.freqs[c] / kC0;
+        du = float(q[0] * sc - u0);
+        dv = float(q[1] * sc - v0);
+        dw = float(q[2] * sc - d.w0);
+        const float4 *vp = reinterpret_cast<const float4 *>(a.vis_in + (bt * a.nr_channels + c) * 4);
+        p0 = vp[0];
+        p1 = vp[1];
+      }
+      s_u[tid] = du;
+      s_v[tid] = dv;
+      s_w[tid] = dw;
+      s_y[0 * CH + tid] = p0.x;
+      s_y[1 * CH + tid] = p0.y;
+      s_y[2 * CH + tid] = p0.z;
+      s_y[3 * CH + tid] = p0.w;
+      s_y[4 * CH + tid] = p1.x;
+      s_y[5 * CH + tid] = p1.y;
+      s_y[6 * CH + tid] = p1.z;
+      s_y[7 * CH + tid] = p1.w;
+      ym = fmaxf(fmaxf(fmaxf(fabsf(p0.x), fabsf(p0.y)), fmaxf(fabsf(p0.z), fabsf(p0.w))),
+                 fmaxf(fmaxf(fabsf(p1.x), fabsf(p1.y)), fmaxf(fabsf(p1.z), fabsf(p1.w))));
+    }
+    __syncthreads();
+    block_max_into(ym, &sm.ybits);
+    __syncthreads();
+    int e = -126;
+    if (sm.ybits) (void)frexpf(__uint_as_float(sm.ybits), &e);  // largest < 2^e
+    if (e > yexp) {
+      const float r = ldexpf(1.0f, yexp - e);
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          gr[n][q] *= r;
+          gi[n][q] *= r;
+        }
+      yexp = e;
+    }
+    const float yinv = ldexpf(1.0f, -yexp);
+    SepOps cur;
+    sep_operands(s_u, s_v, s_w, s_yr, s_yi, kh, xa, yinv, winv, order1, cur);
+    for (int kb = 0; kb < nkp; kb += 16) {
+      SepOps nxt;
+      sep_mfma(cur, order1, gr, gi);
+      if (kb + 16 < nkp) sep_operands(s_u, s_v, s_w, s_yr, s_yi, kb + 16 + kh, xa, yinv, winv, order1, nxt);
+      cur = nxt;
+    }
+    __syncthreads();  // staging and sm.ybits are reused by the next round
+  }
+
+  // S = 2^yexp (G_0 + 2 pi i 2^wexp c G_1), element by element, into LDS
+  const float ys = ldexpf(1.0f, yexp), zs = 6.283185307179586f * ldexpf(1.0f, int(d.wexp));
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int j = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3), i = lane & 31;
+    float2 sv = make_float2(gr[0][e], gi[0][e]);
+    if (order1) {
+      const float z = zs * a.cross[j * L + i];  // i z G_1
+      sv = cadd(sv, make_float2(-z * gi[1][e], z * gr[1][e]));
+    }
+    s_sg[SgLayout<L>::idx(pol, j * L + i)] = make_float2(sv.x * ys, sv.y * ys);
+  }
+  __syncthreads();
+  float2 acc[PPT][4];
+#pragma unroll
+  for (int r = 0; r < PPT; ++r)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[r][p] = s_sg[SgLayout<L>::idx(p, tid + r * NT)];
+  __syncthreads();
+  grid_finish<L>(a, d, local, acc, s_sg, sm.tw);
+}
+
+template <int L>
+__global__ void __launch_bounds__(Cfg<L>::NT) gridder_mfma_kernel(KernelArgs a, const int32_t *order) {
+  __shared__ GridderSmem<L> sm;
+  if (threadIdx.x < L) sm.tw[threadIdx.x] = a.twiddle[threadIdx.x];
+  grid_one_mfma<L>(a, order[blockIdx.x], sm);
+}
+
+// Held to 2 waves per SIMD (the one-subgrid form's budget); the loop would otherwise take 1.
+template <int L>
+__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(2)))
+gridder_mfma_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_head) {
+  __shared__ GridderSmem<L> sm;
+  if (threadIdx.x < L) sm.tw[threadIdx.x] = a.twiddle[threadIdx.x];
+  for (;;) {
+    if (threadIdx.x == 0) sm.next = atomicAdd(queue_head, 1);
+    __syncthreads();
+    const int item = sm.next;
+    if (item >= a.count) break;
+    grid_one_mfma<L>(a, order[item], sm);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Degridder: one workgroup per subgrid.  Split + inverse DFT + A-terms into
 // LDS, then the visibilities are evaluated in tasks of (64 V visibilities x a
 // 1/G share of the pixels): each lane owns V visibilities, so every broadcast
@@ -650,8 +930,10 @@ struct DegridderSmem {
   float2 sg[SG];                            // SgLayout<L>, then [NPIX][4] after the A-terms
   float4 lmn[LMN_LDS ? L * L : 1];
   float2 tw[L];
+  float2 sep[L];                            // separable form: (x_q, a_q)
   float4 part[2 * kDegridPartCap];          // [G][K] partial sums, 4 complex each
   int next;                                 // work-queue item of the persistent form
+  unsigned ybits;                           // separable form: largest |image component| (float bits)
 };
 
 // Sum over the pixel share [lo, hi) for a lane's V visibilities.  RECUR: the V
@@ -982,6 +1264,152 @@ __device__ __forceinline__ void degrid_small(const KernelArgs &a, const DevSubgr
   }
 }
 
+// Degrid subgrid d (32 x 32, d.order in 0..1) by the separable form (the phasor factors of the gridder's
+// separable form, conjugated):
+//   Y_k = sum_j conj(V_k(j)) (T_0[j][k] - 2 pi i dw_k T_1[j][k]),  T_n[j][k] = sum_i (c^n B)[j][i] conj(U_k(i)).
+// Per polarisation (wave) T_n is a (32 x 32)(32 x K) product on the matrix cores: A = the image B (rows j, fp16
+// high/low parts, scaled by a power of two), B = conj(U) of 32 samples (lane l: sample l % 32); then every lane
+// forms conj(V_k(j)) for the 16 rows j of its accumulators and the two half-waves add their dot products.
+// b: this thread's pixels (tid + r NT) after the A-terms and taper; sm.sg is free and sm.ybits zero on entry.
+template <int L>
+__device__ __forceinline__ void degrid_sep(const KernelArgs &a, const DevSubgrid &d, const float2 (&b)[4][4],
+                                           DegridderSmem<L> &sm, double u0, double v0) {
+  static_assert(L == 32 && Cfg<L>::NT == 256, "the matrix-core degridder runs 32 x 32 subgrids on four waves");
+  constexpr int NT = Cfg<L>::NT, PPT = 4, CH = 256;
+  const int tid = threadIdx.x, lane = tid & 63, pol = tid >> 6, hw = lane >> 5, col = lane & 31;
+  const bool order1 = d.order >= 1;
+  const int K = d.nvis;
+  float2 *s_img = sm.sg;
+  float bm = 0.0f;
+#pragma unroll
+  for (int r = 0; r < PPT; ++r)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      bm = fmaxf(bm, fmaxf(fabsf(b[r][e].x), fabsf(b[r][e].y)));
+      s_img[SgLayout<L>::idx(e, threadIdx.x + r * NT)] = b[r][e];
+    }
+  block_max_into(bm, &sm.ybits);
+  __syncthreads();
+  int bexp = -126;
+  if (sm.ybits) (void)frexpf(__uint_as_float(sm.ybits), &bexp);  // largest < 2^bexp
+  const float binv = ldexpf(1.0f, -bexp);
+  // A operands of this wave's polarisation: row j = col, columns i = 16 q + 8 hw + s (s = 0..7)
+  half8 arh[2], arl[2], aih[2], ail[2], acr[2], aci[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    float xr[8], xi[8];
+#pragma unroll
+    for (int s8 = 0; s8 < 8; ++s8) {
+      const int i = 16 * q + 8 * hw + s8;
+      const float2 v = s_img[SgLayout<L>::idx(pol, col * L + i)];
+      xr[s8] = v.x * binv;
+      xi[s8] = v.y * binv;
+    }
+    split_half8(xr, arh[q], arl[q]);
+    split_half8(xi, aih[q], ail[q]);
+    if (order1) {
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int i = 16 * q + 8 * hw + 2 * s2;
+        const float c0 = a.cross[col * L + i], c1 = a.cross[col * L + i + 1];
+        const auto hr = __builtin_amdgcn_cvt_pkrtz(c0 * xr[2 * s2], c1 * xr[2 * s2 + 1]);
+        const auto hi = __builtin_amdgcn_cvt_pkrtz(c0 * xi[2 * s2], c1 * xi[2 * s2 + 1]);
+        acr[q][2 * s2] = hr[0];
+        acr[q][2 * s2 + 1] = hr[1];
+        aci[q][2 * s2] = hi[0];
+        aci[q][2 * s2 + 1] = hi[1];
+      }
+    }
+  }
+  __syncthreads();  // sm.sg holds the staged samples below
+  float *s_u = reinterpret_cast<float *>(sm.sg), *s_v = s_u + CH, *s_w = s_u + 2 * CH;
+  float *s_out = s_u + 3 * CH;  // [4 pols][2][CH]
+  const float bsc = ldexpf(1.0f, bexp), twopi = 6.283185307179586f;
+  for (int k0 = 0; k0 < K; k0 += CH) {
+    const int nk = min(CH, K - k0), nkp = (nk + 31) & ~31;
+    if (tid < nkp) {
+      float du = 0.0f, dv = 0.0f, dw = 0.0f;
+      if (tid < nk) {
+        const uint32_t pk = a.samples[d.vis_offset + k0 + tid];
+        const int t = d.t0 + int(pk >> 16), c = d.c0 + int(pk & 0xffffu);
+        const double *q = a.uvw + (int64_t(d.bl) * a.nr_timesteps + t) * 3;
+        const double sc = a.freqs[c] / kC0;
+        du = float(q[0] * sc - u0);
+        dv = float(q[1] * sc - v0);
+        dw = float(q[2] * sc - d.w0);
+      }
+      s_u[tid] = du;
+      s_v[tid] = dv;
+      s_w[tid] = dw;
+    }
+    __syncthreads();
+    for (int kb = 0; kb < nkp; kb += 32) {
+      const int k = kb + col;  // this lane's sample
+      const float du = s_u[k], dv = s_v[k], dw = s_w[k];
+      floatx16 t0r, t0i, t1r, t1i;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) t0r[e] = t0i[e] = t1r[e] = t1i[e] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        // conj(U_k(i)) = Ur - i Ui for i = 16 q + 8 hw + s
+        float ur[8], ui[8];
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+          const float2 xa = sm.sep[16 * q + 8 * hw + s8];
+          const float pu = __builtin_amdgcn_fractf(du * xa.x + dw * xa.y);
+          ur[s8] = __builtin_amdgcn_cosf(pu);
+          ui[s8] = __builtin_amdgcn_sinf(pu);
+        }
+        half8 urh, url, uih, uil;
+        split_half8(ur, urh, url);
+        split_half8(ui, uih, uil);
+        const half8 nuih = -uih, nuil = -uil;
+        // T_0r += Br Ur + Bi Ui,  T_0i += Bi Ur - Br Ui
+        t0r = mfma_split(arh[q], arl[q], urh, url, t0r);
+        t0i = mfma_split(aih[q], ail[q], urh, url, t0i);
+        t0r = mfma_split(aih[q], ail[q], uih, uil, t0r);
+        t0i = mfma_split(arh[q], arl[q], nuih, nuil, t0i);
+        if (order1) {
+          t1r = __builtin_amdgcn_mfma_f32_32x32x16_f16(acr[q], urh, t1r, 0, 0, 0);
+          t1i = __builtin_amdgcn_mfma_f32_32x32x16_f16(aci[q], urh, t1i, 0, 0, 0);
+          t1r = __builtin_amdgcn_mfma_f32_32x32x16_f16(aci[q], uih, t1r, 0, 0, 0);
+          t1i = __builtin_amdgcn_mfma_f32_32x32x16_f16(acr[q], nuih, t1i, 0, 0, 0);
+        }
+      }
+      // Y_k = sum_j conj(V_k(j)) (T_0 - 2 pi i dw T_1) over this lane's rows j, then the other half-wave's
+      float yr = 0.0f, yi = 0.0f;
+      const float w2 = twopi * dw;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int j = 8 * (e >> 2) + 4 * hw + (e & 3);
+        const float2 xa = sm.sep[j];
+        const float pv = __builtin_amdgcn_fractf(dv * xa.x + dw * xa.y);
+        const float vr = __builtin_amdgcn_cosf(pv), vi = __builtin_amdgcn_sinf(pv);
+        float tr = t0r[e], ti = t0i[e];
+        if (order1) {
+          tr = __builtin_fmaf(w2, t1i[e], tr);
+          ti = __builtin_fmaf(-w2, t1r[e], ti);
+        }
+        yr = __builtin_fmaf(vr, tr, __builtin_fmaf(vi, ti, yr));
+        yi = __builtin_fmaf(vr, ti, __builtin_fmaf(-vi, tr, yi));
+      }
+      yr += __shfl_xor(yr, 32);
+      yi += __shfl_xor(yi, 32);
+      if (hw == 0 && k < nk) {
+        s_out[(2 * pol) * CH + k] = yr * bsc;
+        s_out[(2 * pol + 1) * CH + k] = yi * bsc;
+      }
+    }
+    __syncthreads();
+    if (tid < nk) {
+      float4 *o = reinterpret_cast<float4 *>(a.vis_out + degrid_out_index(a, d, k0 + tid));
+      o[0] = make_float4(s_out[0 * CH + tid], s_out[1 * CH + tid], s_out[2 * CH + tid], s_out[3 * CH + tid]);
+      o[1] = make_float4(s_out[4 * CH + tid], s_out[5 * CH + tid], s_out[6 * CH + tid], s_out[7 * CH + tid]);
+    }
+    __syncthreads();
+  }
+}
+
 // Degrid plan subgrid p (global index) into a.vis_out.  The caller has loaded
 // sm.tw and sm.lmn and synchronises before reusing shared memory.  WIDE: tasks
 // of full-wave lane groups run in the split shape (twice the visibilities per
@@ -989,12 +1417,17 @@ __device__ __forceinline__ void degrid_small(const KernelArgs &a, const DevSubgr
 // subgrid has at most kDegridSmallK visibilities and takes the pixel-owner
 // path; the two paths are separate kernels, so that each gets its own
 // register allocation.
-template <int L, bool FP32_PHASE, bool WIDE, bool SMALL>
+constexpr int kPathLarge = 0, kPathSmall = 1, kPathSep = 2;  // degridder kernels: visibility-per-lane tasks,
+                                                              // pixel-per-lane sums, separable form
+
+template <int L, bool FP32_PHASE, bool WIDE, int PATH>
 __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, DegridderSmem<L> &sm) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT, W = NT / 64;
+  constexpr bool SMALL = PATH == kPathSmall;
   const int tid = threadIdx.x;
   const DevSubgrid d = a.subgrids[p];
   const int N = a.grid_size;
+  if (PATH == kPathSep && tid == 0) sm.ybits = 0u;
 #pragma unroll
   for (int r = 0; r < PPT; ++r) {
     const int pix = tid + r * NT;
@@ -1028,7 +1461,10 @@ __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, Degri
   const double S = a.image_size;
   const double u0 = double(d.x0 + L / 2 - N / 2) / S;
   const double v0 = double(d.y0 + L / 2 - N / 2) / S;
-  if constexpr (SMALL) {
+  if constexpr (PATH == kPathSep) {
+    if constexpr (L == 32) degrid_sep<L>(a, d, b, sm, u0, v0);
+    return;
+  } else if constexpr (SMALL) {
     degrid_small<L, FP32_PHASE>(a, d, b, reinterpret_cast<float4 *>(sm.sg), u0, v0);
     return;
   }
@@ -1109,6 +1545,7 @@ template <int L>
 __device__ __forceinline__ void degrid_load_tables(const KernelArgs &a, DegridderSmem<L> &sm) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L;
   if (threadIdx.x < L) sm.tw[threadIdx.x] = a.twiddle[threadIdx.x];
+  if (threadIdx.x < L && a.sep) sm.sep[threadIdx.x] = a.sep[threadIdx.x];
   if (DegridderSmem<L>::LMN_LDS)
     for (int pix = threadIdx.x; pix < NPIX; pix += NT) sm.lmn[pix] = a.lmn[pix];
 }
@@ -1130,7 +1567,7 @@ __global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu
 degridder_kernel(KernelArgs a, const int32_t *order) {
   __shared__ DegridderSmem<L> sm;
   degrid_load_tables<L>(a, sm);
-  degrid_one<L, FP32_PHASE, WIDE, false>(a, order[blockIdx.x], sm);
+  degrid_one<L, FP32_PHASE, WIDE, kPathLarge>(a, order[blockIdx.x], sm);
 }
 
 template <int L, bool FP32_PHASE>
@@ -1138,14 +1575,19 @@ __global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu
 degridder_small_kernel(KernelArgs a, const int32_t *order) {
   __shared__ DegridderSmem<L> sm;
   degrid_load_tables<L>(a, sm);
-  degrid_one<L, FP32_PHASE, false, true>(a, order[blockIdx.x], sm);
+  degrid_one<L, FP32_PHASE, false, kPathSmall>(a, order[blockIdx.x], sm);
 }
 
-// Persistent form: items order[0 .. count-1] (global subgrid indices, costliest
-// first) through the counter *queue_head (zero before the launch).
-template <int L, bool FP32_PHASE, bool WIDE, bool SMALL>
-__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(degrid_min_waves<L, WIDE>())))
-degridder_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_head) {
+template <int L>
+__global__ void __launch_bounds__(Cfg<L>::NT) degridder_sep_kernel(KernelArgs a, const int32_t *order) {
+  __shared__ DegridderSmem<L> sm;
+  degrid_load_tables<L>(a, sm);
+  degrid_one<L, false, false, kPathSep>(a, order[blockIdx.x], sm);
+}
+
+template <int L>
+__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(2)))
+degridder_sep_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_head) {
   __shared__ DegridderSmem<L> sm;
   degrid_load_tables<L>(a, sm);
   for (;;) {
@@ -1153,7 +1595,25 @@ degridder_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_h
     __syncthreads();
     const int item = sm.next;
     if (item >= a.count) break;
-    degrid_one<L, FP32_PHASE, WIDE, SMALL>(a, order[item], sm);
+    degrid_one<L, false, false, kPathSep>(a, order[item], sm);
+    __syncthreads();
+  }
+}
+
+// Persistent form: items order[0 .. count-1] (global subgrid indices, costliest
+// first) through the counter *queue_head (zero before the launch).
+template <int L, bool FP32_PHASE, bool WIDE, bool SMALL>
+__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(degrid_min_waves<L, WIDE>())))
+degridder_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_head) {
+  constexpr int PATH = SMALL ? kPathSmall : kPathLarge;
+  __shared__ DegridderSmem<L> sm;
+  degrid_load_tables<L>(a, sm);
+  for (;;) {
+    if (threadIdx.x == 0) sm.next = atomicAdd(queue_head, 1);
+    __syncthreads();
+    const int item = sm.next;
+    if (item >= a.count) break;
+    degrid_one<L, FP32_PHASE, WIDE, PATH>(a, order[item], sm);
     __syncthreads();
   }
 }
@@ -1255,7 +1715,7 @@ __global__ void __launch_bounds__(256) combine_kernel(AdderArgs a) {
 }
 
 __global__ void zero_counter_kernel(int32_t *p) {
-  if (threadIdx.x < 2) p[threadIdx.x] = 0;
+  if (threadIdx.x < 4) p[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1346,15 +1806,43 @@ hipError_t noalloc_scratch(void **out) {
     default: return hipErrorInvalidValue;            \
   }
 
-hipError_t launch_gridder(int L, const KernelArgs &a, hipStream_t s) {
+hipError_t launch_gridder(int L, const KernelArgs &a, const int32_t *order, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   IDG_DISPATCH_L(L, {
     if (a.phase_fp32)
-      hipLaunchKernelGGL((gridder_kernel<LL, true>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
+      hipLaunchKernelGGL((gridder_kernel<LL, true>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a, order);
     else
-      hipLaunchKernelGGL((gridder_kernel<LL, false>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a);
+      hipLaunchKernelGGL((gridder_kernel<LL, false>), dim3(a.count), dim3(Cfg<LL>::NT), 0, s, a, order);
   });
   return hipGetLastError();
+}
+
+int separable_max_order() { return kSeparableMaxOrder; }
+bool separable_supported(int L) { return L == 32; }
+
+hipError_t launch_gridder_mfma(int L, const KernelArgs &a, const int32_t *order, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  if (L != 32 || a.phase_fp32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gridder_mfma_kernel<32>), dim3(a.count), dim3(Cfg<32>::NT), 0, s, a, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_gridder_mfma_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
+                                          int nblocks, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  if (L != 32 || a.phase_fp32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, queue_head);
+  hipLaunchKernelGGL((gridder_mfma_persistent_kernel<32>), dim3(nblocks), dim3(Cfg<32>::NT), 0, s, a, order,
+                     queue_head);
+  return hipGetLastError();
+}
+
+int mfma_gridder_blocks_per_cu(int L) {
+  int n = 0;
+  if (L != 32) return 1;
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gridder_mfma_persistent_kernel<32>, Cfg<32>::NT, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 hipError_t launch_gridder_persistent(int L, const KernelArgs &a, const int32_t *order, int32_t *queue_head,
@@ -1372,65 +1860,86 @@ hipError_t launch_gridder_persistent(int L, const KernelArgs &a, const int32_t *
   return hipGetLastError();
 }
 
-// The all-float32 phase variant has no wide form.  order: the cost-sorted list, its first n_large
-// items with more than kDegridSmallK visibilities.
-hipError_t launch_degridder(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_large,
-                            hipStream_t s) {
-  const int64_t n_small = a.count - n_large;
+// The all-float32 phase variant has no wide form.  order: the degridder's work list, order[0 .. n_sep) for the
+// separable form, then n_large subgrids with more than kDegridSmallK visibilities, then the rest.
+hipError_t launch_degridder(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_sep,
+                            int64_t n_large, hipStream_t s) {
+  const int64_t n_small = a.count - n_sep - n_large;
+  if (n_sep > 0) {
+    if (L != 32 || a.phase_fp32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((degridder_sep_kernel<32>), dim3(unsigned(n_sep)), dim3(Cfg<32>::NT), 0, s, a, order);
+  }
+  const int32_t *ol = order + n_sep, *os = order + n_sep + n_large;
   IDG_DISPATCH_L(L, {
     if (n_large > 0) {
       if (a.phase_fp32)
         hipLaunchKernelGGL((degridder_kernel<LL, true, false>), dim3(unsigned(n_large)), dim3(Cfg<LL>::NT), 0, s, a,
-                           order);
+                           ol);
       else if (wide)
         hipLaunchKernelGGL((degridder_kernel<LL, false, true>), dim3(unsigned(n_large)), dim3(Cfg<LL>::NT), 0, s, a,
-                           order);
+                           ol);
       else
         hipLaunchKernelGGL((degridder_kernel<LL, false, false>), dim3(unsigned(n_large)), dim3(Cfg<LL>::NT), 0, s, a,
-                           order);
+                           ol);
     }
     if (n_small > 0) {
       if (a.phase_fp32)
         hipLaunchKernelGGL((degridder_small_kernel<LL, true>), dim3(unsigned(n_small)), dim3(Cfg<LL>::NT), 0, s, a,
-                           order + n_large);
+                           os);
       else
         hipLaunchKernelGGL((degridder_small_kernel<LL, false>), dim3(unsigned(n_small)), dim3(Cfg<LL>::NT), 0, s, a,
-                           order + n_large);
+                           os);
     }
   });
   return hipGetLastError();
 }
 
-// queue_head: two counters (large and small subgrids), zeroed here.
-hipError_t launch_degridder_persistent(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_large,
-                                       int32_t *queue_head, int nblocks_large, int nblocks_small, hipStream_t s) {
+// queue_head: three counters (separable form, large and small subgrids), zeroed here.
+hipError_t launch_degridder_persistent(int L, const KernelArgs &a, bool wide, const int32_t *order, int64_t n_sep,
+                                       int64_t n_large, int32_t *queue_head, int nblocks_sep, int nblocks_large,
+                                       int nblocks_small, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, queue_head);
-  KernelArgs al = a, as = a;
+  KernelArgs ap = a, al = a, as = a;
+  ap.count = int32_t(n_sep);
   al.count = int32_t(n_large);
-  as.count = int32_t(a.count - n_large);
+  as.count = int32_t(a.count - n_sep - n_large);
+  if (ap.count > 0) {
+    if (L != 32 || a.phase_fp32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((degridder_sep_persistent_kernel<32>), dim3(nblocks_sep), dim3(Cfg<32>::NT), 0, s, ap, order,
+                       queue_head + 2);
+  }
+  const int32_t *ol = order + n_sep, *os = order + n_sep + n_large;
   IDG_DISPATCH_L(L, {
     if (al.count > 0) {
       if (a.phase_fp32)
         hipLaunchKernelGGL((degridder_persistent_kernel<LL, true, false, false>), dim3(nblocks_large),
-                           dim3(Cfg<LL>::NT), 0, s, al, order, queue_head);
+                           dim3(Cfg<LL>::NT), 0, s, al, ol, queue_head);
       else if (wide)
         hipLaunchKernelGGL((degridder_persistent_kernel<LL, false, true, false>), dim3(nblocks_large),
-                           dim3(Cfg<LL>::NT), 0, s, al, order, queue_head);
+                           dim3(Cfg<LL>::NT), 0, s, al, ol, queue_head);
       else
         hipLaunchKernelGGL((degridder_persistent_kernel<LL, false, false, false>), dim3(nblocks_large),
-                           dim3(Cfg<LL>::NT), 0, s, al, order, queue_head);
+                           dim3(Cfg<LL>::NT), 0, s, al, ol, queue_head);
     }
     if (as.count > 0) {
       if (a.phase_fp32)
         hipLaunchKernelGGL((degridder_persistent_kernel<LL, true, false, true>), dim3(nblocks_small),
-                           dim3(Cfg<LL>::NT), 0, s, as, order + n_large, queue_head + 1);
+                           dim3(Cfg<LL>::NT), 0, s, as, os, queue_head + 1);
       else
         hipLaunchKernelGGL((degridder_persistent_kernel<LL, false, false, true>), dim3(nblocks_small),
-                           dim3(Cfg<LL>::NT), 0, s, as, order + n_large, queue_head + 1);
+                           dim3(Cfg<LL>::NT), 0, s, as, os, queue_head + 1);
     }
   });
   return hipGetLastError();
+}
+
+int mfma_degridder_blocks_per_cu(int L) {
+  int n = 0;
+  if (L != 32) return 1;
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, degridder_sep_persistent_kernel<32>, Cfg<32>::NT, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 int persistent_blocks_per_cu(int L, bool degrid, bool wide, bool small) {

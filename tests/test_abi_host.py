@@ -169,16 +169,16 @@ def test_empty_plan():
 def test_tuning_round_trip_and_validation():
     p = idg.Plan(**_mini_params())
     assert p.get_tuning() == dict(grid_form="plain", degrid_form="plain", grid_blocks_per_cu=0,
-                                  degrid_blocks_per_cu=0, adder_chunk=0, degrid_shape="standard")
-    p.set_tuning(form="persistent", blocks_per_cu=3, adder_chunk=17, degrid_shape="wide")
+                                  degrid_blocks_per_cu=0, adder_chunk=0, degrid_shape="standard", sum_path="auto")
+    p.set_tuning(form="persistent", blocks_per_cu=3, adder_chunk=17, degrid_shape="wide", sum_path="direct")
     assert p.get_tuning() == dict(grid_form="persistent", degrid_form="persistent", grid_blocks_per_cu=3,
-                                  degrid_blocks_per_cu=3, adder_chunk=17, degrid_shape="wide")
+                                  degrid_blocks_per_cu=3, adder_chunk=17, degrid_shape="wide", sum_path="direct")
     p.set_tuning(degrid_form="plain", grid_blocks_per_cu=2)
     t = p.get_tuning()
     assert (t["grid_form"], t["degrid_form"], t["grid_blocks_per_cu"], t["degrid_blocks_per_cu"]) == (
         "persistent", "plain", 2, 3)
     for bad in (dict(form=7), dict(blocks_per_cu=-1), dict(degrid_blocks_per_cu=65), dict(adder_chunk=-2),
-                dict(degrid_shape=2)):
+                dict(degrid_shape=2), dict(sum_path=5)):
         with pytest.raises(idg.IDGError) as e:
             p.set_tuning(**bad)
         assert e.value.code == -1

@@ -366,3 +366,62 @@ def test_adder_chunks_split_long_tile_lists(gpu):
         x0, y0 = oplan.subgrids[p, F["x0"]], oplan.subgrids[p, F["y0"]]
         ref[:, y0:y0 + L, x0:x0 + L] += sub[p]
     assert max_rel(g.cpu().numpy(), ref) < 1e-6
+
+
+@pytest.mark.parametrize("name", ["lofar-subset", "skalow-subset-flags"])
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+def test_separable_form_matches_oracle(gpu, name, form):
+    # 32 x 32 subgrids whose w-term allows it run the separable form on the matrix cores (sum_path
+    # "auto"); the direct sum ("direct") and the oracle agree with it to float32 level
+    torch, idg = gpu
+    wl, oplan = _case(name)
+    say(f"[separable form] case={name} form={form}")
+    d = to_dev(wl)
+    ref = oidg.grid(oplan, wl.uvw, wl.freqs, wl.vis, wl.aterms, wl.taper)
+    out = {}
+    for path in ("auto", "direct"):
+        plan = idg.Plan.from_workload(wl, scratch_bytes=4 * 32 * 1024 * 8 * 9)
+        plan.set_tuning(form=form, sum_path=path)
+        g = _grid_gpu(torch, idg, wl, plan, d).cpu().numpy()
+        out[path] = g
+        say(f"    {path}: grid rms rel {rms_rel(g, ref):.2e} max rel {max_rel(g, ref):.2e}")
+        assert rms_rel(g, ref) < GRID_RMS_TOL and max_rel(g, ref) < GRID_MAX_TOL, path
+        assert np.all(g[ref == 0] == 0)
+    assert rms_rel(out["auto"], out["direct"]) < GRID_RMS_TOL
+
+
+@pytest.mark.parametrize("name", ["lofar-subset", "skalow-subset-flags"])
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+def test_separable_degridder_matches_oracle(gpu, name, form):
+    # the degridder's separable form (sum_path "auto") and its direct sum ("direct") against the oracle
+    torch, idg = gpu
+    wl, oplan = _case(name)
+    say(f"[separable degridder] case={name} form={form}")
+    d = to_dev(wl)
+    rng = np.random.default_rng(13)
+    N, L = wl.grid_size, wl.subgrid_size
+    grid_in = np.zeros((4, N, N), np.complex64)
+    for p in range(oplan.nr_subgrids):
+        x0, y0 = oplan.subgrids[p, F["x0"]], oplan.subgrids[p, F["y0"]]
+        grid_in[:, y0:y0 + L, x0:x0 + L] = 1.0
+    mask = grid_in != 0
+    grid_in[mask] = (rng.standard_normal(mask.sum()) + 1j * rng.standard_normal(mask.sum())).astype(np.complex64)
+    gdev = torch.from_numpy(grid_in).cuda()
+    ref = oidg.degrid(oplan, wl.uvw, wl.freqs, grid_in, wl.aterms, wl.taper)
+    planned = np.zeros(wl.vis.shape[:3], bool)
+    for p in range(oplan.nr_subgrids):
+        tc = oplan.subgrid_samples(p)
+        planned[oplan.subgrids[p, F["bl"]], tc[:, 0], tc[:, 1]] = True
+    out = {}
+    for path in ("auto", "direct"):
+        plan = idg.Plan.from_workload(wl)
+        plan.set_tuning(form=form, sum_path=path)
+        v = torch.full(tuple(wl.vis.shape), 5.0 + 5.0j, dtype=torch.complex64, device="cuda")
+        idg.degrid(plan, d["uvw"], d["freqs"], gdev, d["aterms"], d["taper"], v)
+        idg.sync()
+        got = v.cpu().numpy()
+        out[path] = got
+        say(f"    {path}: vis rms rel {rms_rel(got[planned], ref[planned]):.2e}")
+        assert rms_rel(got[planned], ref[planned]) < VIS_RMS_TOL, path
+        assert np.all(got[~planned] == 0)
+    assert rms_rel(out["auto"][planned], out["direct"][planned]) < VIS_RMS_TOL
