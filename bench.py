@@ -13,18 +13,30 @@ The headline workload is the SKA-low-like single-GPU share (the largest
 configuration that fits one GPU); the LOFAR-like workload runs as a second
 leg (key "lofar"), with the W-layer and serving legs on its geometry.
 
-Roofline: the gridder and the degridder are bound by the FP32 VALU.  Their
-algorithmic work per launch is counted as
-  34 flop per (visibility, subgrid pixel): one phase multiply-add and 16
-     multiply-adds of the 4-polarisation complex accumulate (sin and cos not
-     counted);
-  136 flop per pixel per subgrid: the two 2 x 2 complex Jones products and the
-     taper;
-  5 L^2 log2(L^2) flop per polarisation per subgrid: the subgrid transform,
-and divided by the kernel's average launch time from HIP events recorded by
-the library on the launching stream.  "roofline" is for the dominant (longer)
-of the two kernels; both are reported.  The CPU baseline is the float64 oracle
-on a bounded sample, timed on this host.
+Roofline.  The gridder and degridder evaluate each subgrid's sums in one of
+two forms (the plan reports which, per subgrid):
+- the direct sum (a phasor per visibility and pixel) on the FP32 VALU; its
+  work, the method's operation count, is
+    34 flop per (visibility, subgrid pixel): one phase multiply-add and 16
+       multiply-adds of the 4-polarisation complex accumulate (sin and cos not
+       counted);
+    136 flop per pixel per subgrid: the two 2 x 2 complex Jones products and
+       the taper;
+    5 L^2 log2(L^2) flop per polarisation per subgrid: the subgrid transform;
+- the separable form (32 x 32 subgrids): per polarisation, complex products
+  (32 x K)(K x 32) of row and column phasor factors on the fp16 matrix cores;
+  its work is 32 flop per (visibility, pixel) for the order-0 product and
+  another 32 for the first-order w cross term.
+When the separable form carries most of a kernel's visibilities the kernel is
+priced as a matrix-core contraction: "achieved" is the separable form's work
+per launch over the launch time, against the dense fp16 peak (the fp16
+high/low operand parts that give 22-bit operands execute 3x the order-0
+products; "executed" reports that rate).  "direct_equivalent" divides the
+method's operation count above by the same time, against the FP32 vector
+peak: the rate a direct-sum kernel would need to match it.  Launch times come
+from HIP events recorded by the library on the launching stream.  "roofline"
+is for the dominant (longer) of the two kernels; both are reported.  The CPU
+baseline is the float64 oracle on a bounded sample, timed on this host.
 """
 
 import argparse
@@ -42,6 +54,10 @@ FLOP_PER_VIS_PIX = 34
 FLOP_PER_PIX_ATERM = 136
 # MI355X FP32 vector peak: 256 CUs x 2 wave64 FMA instructions per CU-cycle x 64 lanes x 2 flop x 2.4 GHz
 FP32_PEAK_TFLOPS = 157.3
+# MI355X dense fp16 matrix-core peak (no structured sparsity)
+FP16_MFMA_PEAK_TFLOPS = 2500.0
+# separable form: flop per (visibility, pixel) of one complex product over 4 polarisations (8 per pol)
+FLOP_PER_VIS_PIX_SEP = 32
 HBM_PEAK_GBS = 8000.0               # MI355X HBM3E
 WORKLOAD_DESC = {
     "skalow": "skalow-like share: 512 stations (130816 baselines), 64 x 1 s, 16 ch 50-350 MHz, L=32, "
@@ -68,6 +84,45 @@ def algorithmic_flops(nvis, nsub, L):
     npix = L * L
     return (FLOP_PER_VIS_PIX * float(nvis) * npix + FLOP_PER_PIX_ATERM * float(npix) * nsub
             + 5.0 * npix * math.log2(npix) * 4 * nsub)
+
+
+def separable_flops(paths, L):
+    """Work of the separable form over one direction: (algorithmic, executed) flops.
+
+    paths: plan.sum_paths(); order-0 subgrids take one complex product per
+    polarisation, order-1 subgrids two.  Executed counts the three high/low
+    products of the order-0 term (the order-1 term takes the high parts only).
+    """
+    n0, n1 = paths["separable0"][1], paths["separable1"][1]
+    npix = L * L
+    alg = FLOP_PER_VIS_PIX_SEP * npix * (float(n0) + 2.0 * n1)
+    exe = FLOP_PER_VIS_PIX_SEP * npix * (3.0 * n0 + 4.0 * n1)
+    return alg, exe
+
+
+def kernel_roofline(flops_direct, paths, L, launch_ms, launches):
+    """The roofline object of one kernel (gridder or degridder) from its average launch time."""
+    t = launch_ms * 1e-3
+    direct = flops_direct / launches / t / 1e12
+    n_sep = paths["separable0"][1] + paths["separable1"][1]
+    out = {"direct_equivalent": {"achieved": round(direct, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": round(direct / FP32_PEAK_TFLOPS, 4)},
+           "sum_paths": paths}
+    if n_sep > paths["direct"][1]:
+        alg, exe = separable_flops(paths, L)
+        achieved = alg / launches / t / 1e12
+        out.update(bound="mfma", achieved=round(achieved, 3), peak=FP16_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                   frac=round(achieved / FP16_MFMA_PEAK_TFLOPS, 5),
+                   executed={"achieved": round(exe / launches / t / 1e12, 3),
+                             "frac": round(exe / launches / t / 1e12 / FP16_MFMA_PEAK_TFLOPS, 5)},
+                   flop_per_launch=alg / launches,
+                   work_per_launch=f"{FLOP_PER_VIS_PIX_SEP} flop x {L * L} pix x ({paths['separable0'][1]} vis "
+                                   f"+ 2 x {paths['separable1'][1]} vis)"
+                                   + (f", over {launches} launches" if launches > 1 else ""))
+    else:
+        out.update(bound="alu", achieved=round(direct, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                   frac=round(direct / FP32_PEAK_TFLOPS, 4), flop_per_launch=flops_direct / launches)
+    return out
 
 
 def hbm_record_path(workload):
@@ -99,10 +154,11 @@ def kernel_traffic(workload, kernel, schedule, path=None):
 
 
 def schedule_string(tuning, kernel):
-    """The part of a plan's tuning that selects `kernel`'s launch shape."""
+    """The part of a plan's tuning that selects `kernel`'s launch shape and sum path."""
+    path = tuning.get("sum_path", "auto")
     if kernel == "gridder":
-        return f"{tuning['grid_form']}/{tuning['grid_blocks_per_cu']}"
-    return f"{tuning['degrid_form']}/{tuning['degrid_blocks_per_cu']}/{tuning['degrid_shape']}"
+        return f"{tuning['grid_form']}/{tuning['grid_blocks_per_cu']}/{path}"
+    return f"{tuning['degrid_form']}/{tuning['degrid_blocks_per_cu']}/{tuning['degrid_shape']}/{path}"
 
 
 def log(*a):
@@ -476,23 +532,21 @@ class Leg:
         flops_step = algorithmic_flops(nvis, nsub, L)
         tuned = self.plan.get_tuning()
         kernels = {}
+        paths = self.plan.sum_paths()
         for kern in ("gridder", "degridder"):
             ms, n = prof[kern]
             launch_ms = ms / max(1, n)
             per_step_launches = max(1, n // k)
-            achieved = (flops_step / per_step_launches) / (launch_ms * 1e-3) / 1e12
-            kernels[kern] = {"bound": "alu", "kernel": kern, "achieved": round(achieved, 3),
-                             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                             "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+            r = kernel_roofline(flops_step, paths, L, launch_ms, per_step_launches)
+            r.setdefault("work_per_launch",
+                         f"({FLOP_PER_VIS_PIX} flop x {nvis} vis + {FLOP_PER_PIX_ATERM} flop x {nsub} subgrids) x "
+                         f"{L * L} pix + 5 L^2 log2(L^2) x 4 pol x {nsub} subgrids"
+                         + (f", over {per_step_launches} launches" if per_step_launches > 1 else ""))
+            kernels[kern] = {"bound": r.pop("bound"), "kernel": kern, "achieved": r.pop("achieved"),
+                             "peak": r.pop("peak"), "unit": r.pop("unit"), "frac": r.pop("frac"),
                              "traffic": kernel_traffic(self.name, kern, schedule_string(tuned, kern)),
                              "traffic_unit": "bytes/launch", "schedule": schedule_string(tuned, kern),
-                             "kernels_sha256": kernel_source_hash(),
-                             "flop_per_launch": flops_step / per_step_launches,
-                             "work_per_launch": f"({FLOP_PER_VIS_PIX} flop x {nvis} vis + "
-                                                f"{FLOP_PER_PIX_ATERM} flop x {nsub} subgrids) x {L * L} pix + "
-                                                f"5 L^2 log2(L^2) x 4 pol x {nsub} subgrids"
-                                                + (f", over {per_step_launches} launches" if per_step_launches > 1
-                                                   else ""),
+                             "kernels_sha256": kernel_source_hash(), **r,
                              "avg_launch_ms": round(launch_ms, 4), "launches_per_step": per_step_launches}
         a_ms, _ = prof["adder"]
         z_ms, _ = prof["zero"]
@@ -507,9 +561,10 @@ class Leg:
                "roofline": kernels[dominant], "gridder_roofline": kernels["gridder"],
                "degridder_roofline": kernels["degridder"], "tuning": tuned}
         self.log(f"[bench] {self.name}: {ms_step:.2f} ms/step, {out['value']:.1f} MVis/s; "
-                 f"gridder {kernels['gridder']['avg_launch_ms']:.3f} ms/launch ({kernels['gridder']['frac']:.1%}), "
+                 f"gridder {kernels['gridder']['avg_launch_ms']:.3f} ms/launch ({kernels['gridder']['frac']:.1%} of "
+                 f"{kernels['gridder']['bound']}), "
                  f"adder {a_ms / k:.3f} ms, degridder {kernels['degridder']['avg_launch_ms']:.3f} ms/launch "
-                 f"({kernels['degridder']['frac']:.1%})")
+                 f"({kernels['degridder']['frac']:.1%} of {kernels['degridder']['bound']})")
         return out
 
     def config(self):

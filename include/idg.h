@@ -139,6 +139,17 @@ int idg_plan(const idg_params *params, const int32_t *baselines, const double *u
 int idg_plan_stats(idg_plan_t plan, int64_t *nr_subgrids, int64_t *nr_gridded, int64_t *nr_dropped,
                    int64_t *nr_flagged);
 
+/* How the subgrid sums of the plan are evaluated under its current tuning and
+ * precision (either pointer may be NULL; each is int64 [3]):
+ *   [0] separable form, cross term to order 0;  [1] separable form, order 1;
+ *   [2] direct sum (phasor per sample and pixel, eq. 14 and its adjoint).
+ * nr_subgrids counts subgrids, nr_vis their planned samples.  The separable form
+ * factors the phasor of eq. 14 into a row factor and a column factor (the
+ * phase is linear in the offsets of section 3.1) times a bounded expansion of
+ * the non-separable remainder of n'; it applies to 32 x 32 subgrids in
+ * float64-offset precision with sum_path IDG_SUM_AUTO. */
+int idg_plan_sum_paths(idg_plan_t plan, int64_t *nr_subgrids, int64_t *nr_vis);
+
 /* W-layers of the plan (either pointer may be NULL): the grid passed to
  * idg_grid / idg_degrid is [nr_wlayers][4][N][N], layer index j - wlayer_min.
  * Without layers wlayer_min = 0 and nr_wlayers = 1. */
@@ -150,8 +161,9 @@ int idg_plan_wlayers(idg_plan_t plan, int32_t *wlayer_min, int32_t *nr_wlayers);
  *             grouped by subgrid (rows vis_offset .. vis_offset + nvis - 1), t-major. */
 int idg_plan_export(idg_plan_t plan, int64_t *subgrids, int32_t *samples);
 
-/* Scheduling knobs of a plan (the path's schedule, not its arithmetic: every
- * setting gives the same result up to float32 summation order in the adder).
+/* Scheduling knobs of a plan (the path's schedule: every setting but sum_path
+ * gives the same result up to float32 summation order; sum_path selects
+ * between two evaluations of the subgrid sums that agree to float32 level).
  *   grid_form, degrid_form
  *                  IDG_FORM_PLAIN: one workgroup per subgrid;
  *                  IDG_FORM_PERSISTENT: a fixed set of workgroups takes subgrids
@@ -220,7 +232,7 @@ void idg_plan_destroy(idg_plan_t plan);
  * evaluation to float32 rounding.  Subgrids of 32 x 32 may instead run the
  * separable form (tuning sum_path): with n' = a(l) + a(m) + c(l, m),
  * a(x) = sqrt(1 - x^2) - 1, the phasor is U(l) V(m) exp(2 pi i dw c), the
- * last factor expanded to the order (at most 2) that keeps its truncation
+ * last factor expanded to the order (0 or 1) that keeps its truncation
  * below 1e-6 given the subgrid's largest |w - w_0p| (the plan computes it in
  * float64); each order is a dense (32 x K)(K x 32) product per polarisation,
  * on the matrix cores with fp16 high/low operand parts.  Subgrids whose

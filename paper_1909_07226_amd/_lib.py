@@ -24,7 +24,7 @@ EXPORTED = ("idg_plan", "idg_plan_stats", "idg_plan_export", "idg_plan_destroy",
             "idg_last_error", "idg_version", "idg_profile", "idg_profile_read", "idg_plan_set_tuning",
             "idg_plan_get_tuning", "idg_grid_to_image", "idg_image_to_grid", "idg_taper_optimal",
             "idg_taper_correction", "idg_plan_wlayers", "idg_wstack_to_image", "idg_image_to_wstack",
-            "idg_grid_noalloc")
+            "idg_grid_noalloc", "idg_plan_sum_paths")
 NOALLOC_SCRATCH_BYTES = 128 << 20          # IDG_NOALLOC_SCRATCH_BYTES
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 DEGRID_STANDARD, DEGRID_WIDE = 0, 1
@@ -97,6 +97,7 @@ def lib():
         L.idg_taper_optimal.argtypes = [i32, ctypes.c_double, vp, vp]
         L.idg_taper_correction.argtypes = [i32, ctypes.c_double, vp, i32, vp]
         L.idg_plan_wlayers.argtypes = [vp, vp, vp]
+        L.idg_plan_sum_paths.argtypes = [vp, vp, vp]
         L.idg_wstack_to_image.argtypes = [vp, i32, vp, i32, ctypes.c_double, vp, vp, vp, vp]
         L.idg_image_to_wstack.argtypes = [vp, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp]
         for name in EXPORTED:
@@ -193,6 +194,14 @@ class Plan:
         v = [ctypes.c_int64() for _ in range(4)]
         check(lib().idg_plan_stats(self._handle, *[ctypes.byref(x) for x in v]))
         return dict(zip(("nr_subgrids", "nr_gridded", "nr_dropped", "nr_flagged"), (x.value for x in v)))
+
+    def sum_paths(self):
+        """Subgrids and samples per evaluation of the subgrid sums under the current tuning:
+        {"separable0": (subgrids, samples), "separable1": ..., "direct": ...}."""
+        ns = (ctypes.c_int64 * 3)()
+        nv = (ctypes.c_int64 * 3)()
+        check(lib().idg_plan_sum_paths(self._handle, ns, nv))
+        return {k: (int(ns[i]), int(nv[i])) for i, k in enumerate(("separable0", "separable1", "direct"))}
 
     @property
     def nr_subgrids(self):

@@ -3,13 +3,14 @@
 Candidates are timed on the plan's own data with the library's HIP-event stage
 timers (idg_profile): gridder and degridder in the plain form and in the
 persistent work-queue form at several workgroups per compute unit, the
-degridder in its standard and wide shapes, and the adder at several chunk
-lengths.  The fastest setting of each stage wins; the
-choice is stored on the plan and cached per (device, L, N, plan shape) in a
-JSON file (``$IDG_TUNING_CACHE`` or ``~/.cache/paper_1909_07226_amd/tuning.json``).
-Tuning changes the schedule only: results are identical for the gridder and
-degridder forms and equal up to float32 summation order for the degridder
-shapes and the adder chunks.
+degridder in its standard and wide shapes, the adder at several chunk
+lengths, and, where the plan has subgrids in the separable form, the direct
+sum instead (the two sum paths agree to float32 level).  The fastest setting
+of each stage wins; the choice is stored on the plan and cached per (device,
+L, N, plan shape) in a JSON file (``$IDG_TUNING_CACHE`` or
+``~/.cache/paper_1909_07226_amd/tuning.json``).  Results are identical for the
+gridder and degridder forms and equal up to float32 summation order for the
+degridder shapes and the adder chunks.
 """
 
 import json
@@ -36,7 +37,7 @@ def plan_key(plan):
     mean_k = st["nr_gridded"] / n
     dev = torch.cuda.get_device_properties(torch.cuda.current_device())
     arch = getattr(dev, "gcnArchName", dev.name)
-    return (f"v3|{arch}|L{plan.subgrid_size}|N{plan.grid_size}|P2^{int(np.log2(n))}"
+    return (f"v4|{arch}|L{plan.subgrid_size}|N{plan.grid_size}|P2^{int(np.log2(n))}"
             f"|K2^{int(np.log2(max(1.0, mean_k)))}")
 
 
@@ -99,6 +100,7 @@ def autotune(plan, uvw, freqs, vis, aterms, taper, grid, vis_out=None, reps=2, u
     def do_degrid():
         _lib.degrid(plan, uvw, freqs, grid, aterms, taper, vis_out, stream)
 
+    plan.set_tuning(sum_path="auto")
     best_g = best_d = None
     for form, bpc in GRID_CANDIDATES:
         plan.set_tuning(grid_form=form, degrid_form=form, grid_blocks_per_cu=bpc, degrid_blocks_per_cu=bpc)
@@ -122,6 +124,21 @@ def autotune(plan, uvw, freqs, vis, aterms, taper, grid, vis_out=None, reps=2, u
             log(f"[autotune] {form}/{bpc}: gridder {tg:.3f} ms, degridder " + ", ".join(tds))
     plan.set_tuning(grid_form=best_g[1], grid_blocks_per_cu=best_g[2], degrid_form=best_d[1],
                     degrid_blocks_per_cu=best_d[2], degrid_shape=best_d[3])
+    paths = plan.sum_paths()
+    if paths["separable0"][0] + paths["separable1"][0] > 0:
+        # one knob for both directions: keep the path with the smaller gridder + degridder time
+        plan.set_tuning(sum_path="direct")
+        do_grid()
+        do_degrid()
+        _lib.sync(stream)
+        tg = _stage_ms(do_grid, "gridder", reps, stream)
+        td = _stage_ms(do_degrid, "degridder", reps, stream)
+        timings["sum_path/direct"] = round(tg + td, 4)
+        timings["sum_path/auto"] = round(best_g[0] + best_d[0], 4)
+        if log:
+            log(f"[autotune] sum path: auto {best_g[0] + best_d[0]:.3f} ms, direct {tg + td:.3f} ms")
+        if tg + td >= best_g[0] + best_d[0]:
+            plan.set_tuning(sum_path="auto")
     best_c = None
     for chunk in CHUNK_CANDIDATES:
         plan.set_tuning(adder_chunk=chunk)

@@ -266,6 +266,13 @@ int separable_order(double wmax, double cmax, int max_order) {
   return -1;
 }
 
+// Whether the plan's subgrids may take the separable form (subgrid size, precision and tuning).
+bool separable_on(const idg_plan_s *plan) {
+  const idg_params &p = plan->host.params;
+  return idg::separable_supported(p.subgrid_size) && !(p.flags & IDG_PHASE_FP32) &&
+         plan->tuning.sum_path == IDG_SUM_AUTO;
+}
+
 void lmn_table(int L, double S, std::vector<float4> &lmn, std::vector<float2> &tw) {
   lmn.resize(size_t(L) * L);
   for (int j = 0; j < L; ++j)
@@ -322,9 +329,7 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
   std::vector<float> cross;
   const double cmax = separable_tables(L, p.image_size, sep, cross);
   // separable form: the expansion order and the power-of-two bound of |w - w_0p| per subgrid
-  const bool sep_on = idg::separable_supported(L) && !(p.flags & IDG_PHASE_FP32) &&
-                      plan->tuning.sum_path == IDG_SUM_AUTO;
-  if (sep_on)
+  if (separable_on(plan))
     for (size_t i = 0; i < subs.size(); ++i) {
       const double wm = plan->wmax[i];
       int e = 0;
@@ -550,6 +555,32 @@ int idg_plan_stats(idg_plan_t plan, int64_t *nr_subgrids, int64_t *nr_gridded, i
   if (nr_gridded) *nr_gridded = plan->host.nr_gridded;
   if (nr_dropped) *nr_dropped = plan->host.nr_dropped;
   if (nr_flagged) *nr_flagged = plan->host.nr_flagged;
+  return IDG_OK;
+}
+
+int idg_plan_sum_paths(idg_plan_t plan, int64_t *nr_subgrids, int64_t *nr_vis) {
+  if (!plan) return fail(IDG_EINVAL, "idg_plan_sum_paths: plan is NULL");
+  int64_t ns[3] = {0, 0, 0}, nv[3] = {0, 0, 0};
+  const idg::HostPlan &h = plan->host;
+  std::lock_guard<std::mutex> lock(plan->mu);
+  if (separable_on(plan)) {
+    std::vector<float2> sep;
+    std::vector<float> cross;
+    const double cmax = separable_tables(h.params.subgrid_size, h.params.image_size, sep, cross);
+    for (size_t i = 0; i < h.subgrids.size(); ++i) {
+      const int n = separable_order(plan->wmax[i], cmax, idg::separable_max_order());
+      const int k = n < 0 ? 2 : n;
+      ns[k] += 1;
+      nv[k] += h.subgrids[i].nvis;
+    }
+  } else {
+    ns[2] = int64_t(h.subgrids.size());
+    for (const auto &r : h.subgrids) nv[2] += r.nvis;
+  }
+  for (int k = 0; k < 3; ++k) {
+    if (nr_subgrids) nr_subgrids[k] = ns[k];
+    if (nr_vis) nr_vis[k] = nv[k];
+  }
   return IDG_OK;
 }
 

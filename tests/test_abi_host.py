@@ -220,3 +220,54 @@ def test_grid_noalloc_validates_before_any_device_call():
     L.idg_last_error.restype = ctypes.c_char_p
     assert b"NULL" in L.idg_last_error()
     assert idg.NOALLOC_SCRATCH_BYTES == 128 << 20
+
+
+def _expected_sum_paths(wl, p, w_step=0.0):
+    """Per-subgrid evaluation of the sums, from the plan's samples in float64: order 0 or 1 of the
+    separable form where the truncation of exp(2 pi i dw c) stays below 1e-6, else the direct sum."""
+    L, S = wl.subgrid_size, wl.image_size
+    x = (np.arange(L) - L // 2) * (S / L)
+    a = np.sqrt(1.0 - x * x) - 1.0
+    n2 = np.sqrt(1.0 - x[None, :] ** 2 - x[:, None] ** 2) - 1.0
+    cmax = np.abs(n2 - a[None, :] - a[:, None]).max()
+    sub, smp = p.export()
+    cols = idg.SUBGRID_FIELDS
+    ns, nv = [0, 0, 0], [0, 0, 0]
+    for r in sub:
+        bl, off, nvis, layer = r[cols.index("bl")], r[cols.index("vis_offset")], r[cols.index("nvis")], \
+            r[cols.index("wlayer")]
+        t, c = smp[off:off + nvis, 0], smp[off:off + nvis, 1]
+        w = wl.uvw[bl, t, 2] * wl.freqs[c] / 299792458.0 - layer * w_step
+        theta = 2 * np.pi * np.abs(w).max() * cmax
+        k = 0 if theta <= 1e-6 else (1 if theta * theta / 2 <= 1e-6 else 2)
+        ns[k] += 1
+        nv[k] += int(nvis)
+    return {"separable0": (ns[0], nv[0]), "separable1": (ns[1], nv[1]), "direct": (ns[2], nv[2])}
+
+
+@pytest.mark.parametrize("name", ["lofar", "skalow"])
+def test_sum_paths_follow_the_truncation_rule(name):
+    full = synth.make_workload(name, with_vis=False)
+    wl = synth.subset(full, baselines=np.arange(0, full.nr_baselines, 97 if name == "lofar" else 1031))
+    p = idg.Plan.from_workload(wl)
+    got = p.sum_paths()
+    assert got == _expected_sum_paths(wl, p)
+    st = p.stats()
+    assert sum(v[0] for v in got.values()) == st["nr_subgrids"]
+    assert sum(v[1] for v in got.values()) == st["nr_gridded"]
+    assert got["separable0"][0] + got["separable1"][0] > 0
+    p.set_tuning(sum_path="direct")
+    assert p.sum_paths() == {"separable0": (0, 0), "separable1": (0, 0),
+                             "direct": (st["nr_subgrids"], st["nr_gridded"])}
+
+
+def test_sum_paths_direct_for_other_subgrid_sizes_and_fp32_offsets():
+    wl = synth.make_workload("tiny", with_vis=False)      # L = 24
+    p = idg.Plan.from_workload(wl)
+    st = p.stats()
+    assert p.sum_paths()["direct"] == (st["nr_subgrids"], st["nr_gridded"])
+    full = synth.make_workload("lofar", with_vis=False)
+    wl = synth.subset(full, baselines=np.arange(0, full.nr_baselines, 211))
+    p = idg.Plan.from_workload(wl, phase_fp32=True)
+    st = p.stats()
+    assert p.sum_paths()["direct"] == (st["nr_subgrids"], st["nr_gridded"])

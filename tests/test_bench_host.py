@@ -58,8 +58,28 @@ def test_traffic_record_requires_matching_kernel_source(tmp_path, monkeypatch):
 def test_schedule_string():
     t = dict(grid_form="persistent", degrid_form="plain", grid_blocks_per_cu=0, degrid_blocks_per_cu=2,
              adder_chunk=64, degrid_shape="wide")
-    assert bench.schedule_string(t, "gridder") == "persistent/0"
-    assert bench.schedule_string(t, "degridder") == "plain/2/wide"
+    assert bench.schedule_string(t, "gridder") == "persistent/0/auto"
+    assert bench.schedule_string(t, "degridder") == "plain/2/wide/auto"
+    t["sum_path"] = "direct"
+    assert bench.schedule_string(t, "gridder") == "persistent/0/direct"
+
+
+def test_kernel_roofline_prices_the_separable_form_on_the_matrix_cores():
+    L = 32
+    # all visibilities in the separable form, half of them with the first-order term
+    paths = {"separable0": (10, 1000), "separable1": (10, 1000), "direct": (0, 0)}
+    alg, exe = bench.separable_flops(paths, L)
+    assert alg == 32 * 1024 * (1000 + 2 * 1000)
+    assert exe == 32 * 1024 * (3 * 1000 + 4 * 1000)
+    r = bench.kernel_roofline(1e12, paths, L, launch_ms=2.0, launches=1)
+    assert r["bound"] == "mfma" and r["peak"] == bench.FP16_MFMA_PEAK_TFLOPS
+    assert abs(r["achieved"] - round(alg / 2e-3 / 1e12, 3)) < 1e-9
+    assert r["direct_equivalent"]["achieved"] == 500.0       # 1e12 flop in 2 ms
+    assert r["direct_equivalent"]["peak"] == bench.FP32_PEAK_TFLOPS
+    # mostly direct sums: the FP32 vector roofline
+    paths = {"separable0": (1, 10), "separable1": (0, 0), "direct": (10, 1000)}
+    r = bench.kernel_roofline(1e12, paths, L, launch_ms=10.0, launches=2)
+    assert r["bound"] == "alu" and r["achieved"] == 50.0 and r["frac"] == round(50.0 / 157.3, 4)
 
 
 def test_committed_traffic_records_are_parseable():
