@@ -518,7 +518,8 @@ class Leg:
             tune_info = autotune(plan, self.uvw, self.freqs, self.vis, self.aterms, self.taper, self.grid,
                                  self.vis_out, use_cache=False, log=self.log)
         else:
-            plan.set_tuning(form=args.form, blocks_per_cu=args.blocks_per_cu, degrid_shape=args.degrid_shape)
+            plan.set_tuning(form=args.form, blocks_per_cu=args.blocks_per_cu, degrid_shape=args.degrid_shape,
+                            sum_path=args.sum_path)
         if args.adder_chunk:
             plan.set_tuning(adder_chunk=args.adder_chunk)
         return tune_info
@@ -621,6 +622,8 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent form: workgroups per CU (0 = max)")
     ap.add_argument("--degrid-shape", default="standard", choices=("standard", "wide"),
                     help="degridder task shape when --form is given (autotuned otherwise)")
+    ap.add_argument("--sum-path", default="auto", choices=("auto", "direct"),
+                    help="with --form plain/persistent: separable form where it applies, or the direct sum")
     ap.add_argument("--adder-chunk", type=int, default=0, help="adder: longest tile-list run per workgroup (0 = 256)")
     ap.add_argument("--no-lofar", action="store_true",
                     help="skip the LOFAR-like leg (and the W-layer and serving legs on its geometry)")

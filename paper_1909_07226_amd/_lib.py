@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libidg.so")
+# IDG_LIBRARY: another build of the same library (the host-sanitized one of build.py)
+LIB_PATH = os.environ.get("IDG_LIBRARY") or os.path.join(_HERE, "libidg.so")
 
 IDG_OK, IDG_EINVAL, IDG_ENOMEM, IDG_EHIP, IDG_ERANGE, IDG_ESTATE = 0, -1, -2, -3, -4, -5
 IDG_STRICT = 1 << 0
