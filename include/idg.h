@@ -289,8 +289,11 @@ int idg_degrid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, cons
  * first .. first + count - 1 of the plan and write each subgrid to
  * out_d[count][4][L][L] complex64 ([pol][row m / v][col l / u]), either as the
  * image after A-terms and taper (stage 0, before the transform) or as the uv
- * subgrid after the centred DFT (stage 1).  Nothing is added to a grid.
- * Errors: IDG_EINVAL (range or stage), IDG_EHIP.
+ * subgrid after the centred DFT (stage 1).  Nothing is added to a grid.  The
+ * subgrid sums take the same form as in idg_grid (idg_plan_sum_paths); when
+ * some take the separable form, the call uploads a work list and synchronises
+ * the stream once.
+ * Errors: IDG_EINVAL (range or stage), IDG_ENOMEM, IDG_EHIP.
  */
 int idg_grid_subgrids(idg_plan_t plan, const double *uvw_d, const double *freqs_d, const idg_cf32 *vis_d,
                       const idg_cf32 *aterms_d, const float *taper_d, int64_t first, int64_t count, int32_t stage,

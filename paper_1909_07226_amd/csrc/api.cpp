@@ -70,6 +70,7 @@ struct DevPlan {
   int64_t batch_size = 0, max_slots = 0;
   int64_t degrid_n_sep = 0;    // leading entries of degrid_order in the separable form
   int64_t degrid_n_large = 0;  // then the entries above the small-subgrid threshold
+  std::vector<int16_t> order;  // host copy of each subgrid's separable-form order (-1: direct sum)
 
   ~DevPlan() {
     int cur = -1;
@@ -337,6 +338,8 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
       subs[i].order = int16_t(separable_order(wm, cmax, idg::separable_max_order()));
       subs[i].wexp = int16_t(std::max(-120, std::min(120, e)));
     }
+  dp->order.resize(subs.size());
+  for (size_t i = 0; i < subs.size(); ++i) dp->order[i] = subs[i].order;
   int rc;
   if ((rc = upload(&dp->subgrids, subs.data(), subs.size(), "plan upload (subgrids)")) != IDG_OK) return rc;
   if ((rc = upload(&dp->samples, h.samples.data(), h.samples.size(), "plan upload (samples)")) != IDG_OK) return rc;
@@ -661,9 +664,36 @@ int idg_grid_subgrids(idg_plan_t plan, const double *uvw_d, const double *freqs_
   const int L = plan->host.params.subgrid_size;
   for (int64_t f = 0; f < count; f += (int64_t(1) << 30)) {
     a.first = first + f;
-    a.count = int32_t(std::min<int64_t>(count - f, int64_t(1) << 30));
+    const int32_t n = int32_t(std::min<int64_t>(count - f, int64_t(1) << 30));
     a.subgrids_out = reinterpret_cast<float2 *>(out_d) + f * 4 * L * L;
-    HIP_TRY(idg::launch_gridder(L, a, nullptr, s), "gridder launch");
+    // as idg_grid: subgrids with an order >= 0 take the separable form, the others the direct sum
+    std::vector<int32_t> ord;
+    for (int32_t i = 0; i < n; ++i)
+      if (dp->order[size_t(a.first + i)] >= 0) ord.push_back(i);
+    const int32_t n_sep = int32_t(ord.size());
+    if (n_sep == 0) {
+      a.count = n;
+      HIP_TRY(idg::launch_gridder(L, a, nullptr, s), "gridder launch");
+      continue;
+    }
+    for (int32_t i = 0; i < n; ++i)
+      if (dp->order[size_t(a.first + i)] < 0) ord.push_back(i);
+    int32_t *ord_d = nullptr;
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&ord_d), ord.size() * sizeof(int32_t), s),
+            "idg_grid_subgrids: order list");
+    hipError_t e = hipMemcpyAsync(ord_d, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host list goes out of scope
+    if (e == hipSuccess) {
+      a.count = n_sep;
+      e = idg::launch_gridder_mfma(L, a, ord_d, s);
+    }
+    if (e == hipSuccess && n > n_sep) {
+      a.count = n - n_sep;
+      e = idg::launch_gridder(L, a, ord_d + n_sep, s);
+    }
+    const hipError_t ef = hipFreeAsync(ord_d, s);
+    HIP_TRY(e, "idg_grid_subgrids: gridder launch");
+    HIP_TRY(ef, "idg_grid_subgrids: order list release");
   }
   return IDG_OK;
 }

@@ -6,11 +6,16 @@
 //                 / (corr_m[y] corr_l[x])
 //
 // and its adjoint.  For N a power of two the centred 1-D transform is
-// (-1)^k FFT[(-1)^n x].  The 2-D transform is two passes over HBM: one over
-// rows (contiguous), one over blocks of C adjacent columns, each workgroup
-// holding whole transforms in LDS.  The column pass reads and writes C x 8
-// bytes per row; its blocks are mapped so that neighbours sharing cache lines
-// run on one XCD (one L2).  The division is fused into the column pass.
+// (-1)^k FFT[(-1)^n x].  Up to N = 1024 the 2-D transform is two passes over
+// HBM: one over rows (contiguous), one over blocks of C adjacent columns, each
+// workgroup holding whole transforms in LDS.  The column pass reads and writes
+// C x 8 bytes per row; its blocks are mapped so that neighbours sharing cache
+// lines run on one XCD (one L2).  From N = 2048 on, fewer than 16 whole
+// columns fit in LDS, and the column transform takes the four-step form
+// (N = N1 N2: length-N1 transforms over runs of consecutive rows, twiddles,
+// length-N2 transforms over rows N1 apart), so the 2-D transform is three
+// passes: the rows (gathered into the four-step order), step A and step B.
+// The division is fused into the last pass (first, in the adjoint).
 //
 // Inside a workgroup: radix-2 decimation in frequency, three stages at a time
 // in registers (a closed set of 8 elements per work item), one LDS round trip

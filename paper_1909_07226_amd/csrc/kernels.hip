@@ -103,14 +103,14 @@ __device__ __forceinline__ void apply_aterms_degrid(const float2 *j1, const floa
 }
 
 // ---------------------------------------------------------------------------
-// Subgrid layout in LDS: [4][L][RS] complex.  Power-of-two sizes are
-// transformed by a register FFT per row / column; their rows are padded to
-// RS = L + 1 so that the lanes of a wave, each walking its own row, hit
-// different LDS banks.
+// Subgrid layout in LDS: [4][L][RS] complex.  Every supported size (2^n and
+// 3 x 2^n) is transformed by a register FFT per row / column; the rows are
+// padded to RS = L + 1 so that the lanes of a wave, each walking its own row,
+// hit different LDS banks.
 
 template <int L>
 struct SgLayout {
-  static constexpr bool FFT = (L == 8 || L == 16 || L == 32 || L == 64);
+  static constexpr bool FFT = (L == 8 || L == 16 || L == 24 || L == 32 || L == 48 || L == 64);
   static constexpr int RS = FFT ? L + 1 : L;  // row stride
   static constexpr int POL = L * RS;          // polarisation stride
   static constexpr int SIZE = 4 * POL;        // complex elements
@@ -156,9 +156,54 @@ constexpr int bit_reverse(int i, int n) {
   return r;
 }
 
-// In-register radix-2 FFT, X[k] = sum_n x[n] exp(-+2 pi i n k / N) (INV: +), unnormalised.
+template <int N, bool INV>
+__device__ __forceinline__ void reg_fft(float2 (&x)[N]);
+
+// N = 3M, M a power of two: decimation in time by 3.  With F_r the M-point
+// transforms of x[3m + r] and W = exp(-+2 pi i / N),
+//   X[k + M q] = sum_r exp(-+2 pi i r q / 3) W^(r k) F_r[k],  k < M, q = 0, 1, 2,
+// a radix-3 butterfly per k on (F_0, W^k F_1, W^2k F_2).
+template <int N, bool INV>
+__device__ __forceinline__ void reg_fft_radix3(float2 (&x)[N]) {
+  constexpr int M = N / 3;
+  constexpr Twiddles<N> T{};
+  constexpr float kS3 = 0.86602540378443865f;  // sin(pi / 3)
+  float2 f[3][M];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) f[r][m] = x[3 * m + r];
+    reg_fft<M, INV>(f[r]);
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const float2 a = f[0][k];
+    float2 b = f[1][k], c = f[2][k];
+    if (k != 0) {
+      const float w1r = T.re[k], w1i = INV ? -T.im[k] : T.im[k];
+      const float w2r = T.re[2 * k], w2i = INV ? -T.im[2 * k] : T.im[2 * k];
+      b = make_float2(b.x * w1r - b.y * w1i, b.x * w1i + b.y * w1r);
+      c = make_float2(c.x * w2r - c.y * w2i, c.x * w2i + c.y * w2r);
+    }
+    // exp(-+2 pi i / 3) = -1/2 -+ i sin(pi / 3):  X1 = a - (b + c) / 2 -+ i s (b - c), X2 = its mirror
+    const float2 sum = make_float2(b.x + c.x, b.y + c.y), dif = make_float2(b.x - c.x, b.y - c.y);
+    const float2 mid = make_float2(a.x - 0.5f * sum.x, a.y - 0.5f * sum.y);
+    const float2 rot = INV ? make_float2(-kS3 * dif.y, kS3 * dif.x) : make_float2(kS3 * dif.y, -kS3 * dif.x);
+    x[k] = make_float2(a.x + sum.x, a.y + sum.y);
+    x[k + M] = make_float2(mid.x + rot.x, mid.y + rot.y);
+    x[k + 2 * M] = make_float2(mid.x - rot.x, mid.y - rot.y);
+  }
+}
+
+// In-register FFT, X[k] = sum_n x[n] exp(-+2 pi i n k / N) (INV: +), unnormalised: radix 2 for
+// N = 2^n, one radix-3 step and then radix 2 for N = 3 x 2^n.
 template <int N, bool INV>
 __device__ __forceinline__ void reg_fft(float2 (&x)[N]) {
+  if constexpr (N % 3 == 0) {
+    reg_fft_radix3<N, INV>(x);
+    return;
+  } else {
+  static_assert((N & (N - 1)) == 0, "reg_fft: N = 2^n or 3 x 2^n");
   constexpr Twiddles<N> T{};
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -191,6 +236,7 @@ __device__ __forceinline__ void reg_fft(float2 (&x)[N]) {
       }
     }
   }
+  }
 }
 
 // Centred 2-D DFT of a [4][L][L] subgrid held in LDS, in place:
@@ -198,14 +244,14 @@ __device__ __forceinline__ void reg_fft(float2 (&x)[N]) {
 // w(k) = exp(-+2 pi i k / L) (INV: +).  For even L this is
 //   out = (-1)^(a+b) FFT2[(-1)^(i+j) in],
 // done as register FFTs per (polarisation, row) and then per (polarisation,
-// column), two threads per line.  Other sizes use a direct DFT per output
-// (twiddle table `tw`).
+// column), two threads per line; `tw` holds exp(-2 pi i k / L), k < L.
 template <int L, int NT, bool INV>
 __device__ __forceinline__ void lds_centred_dft(float2 *sg, const float2 *tw) {
   using Lay = SgLayout<L>;
   constexpr int NPIX = L * L, PPT = NPIX / NT, H = L / 2;
   const int tid = threadIdx.x;
-  if constexpr (Lay::FFT) {
+  static_assert(Lay::FFT, "subgrid transform: L = 2^n or 3 x 2^n");
+  {
     // Each line (a row in pass 0, a column in pass 1, of one polarisation) is
     // transformed by two threads: thread h takes the samples n = 2j + h and does
     // an L/2-point FFT in registers; after a barrier, each thread forms half of
@@ -271,44 +317,6 @@ __device__ __forceinline__ void lds_centred_dft(float2 *sg, const float2 *tw) {
       }
       __syncthreads();
     }
-  } else {
-    const float sgn = INV ? -1.0f : 1.0f;
-#pragma unroll 1
-    for (int pass = 0; pass < 2; ++pass) {
-      float2 res[PPT][4];
-#pragma unroll
-      for (int r = 0; r < PPT; ++r) {
-        const int pix = tid + r * NT;
-        const int row = pix / L, col = pix % L;
-        // pass 0: transform along a row (output column `col`); pass 1: along a column (output row `row`)
-        const int kout = (pass == 0 ? col : row) - H;
-        int idx = (kout * -H) % L;
-        if (idx < 0) idx += L;
-        float2 acc[4] = {};
-#pragma unroll 8
-        for (int q = 0; q < L; ++q) {
-          float2 w = tw[idx];
-          w.y *= sgn;
-          const int src = pass == 0 ? row * L + q : q * L + col;
-#pragma unroll
-          for (int pol = 0; pol < 4; ++pol) {
-            const float2 x = sg[pol * NPIX + src];
-            acc[pol].x += x.x * w.x - x.y * w.y;
-            acc[pol].y += x.x * w.y + x.y * w.x;
-          }
-          idx += kout;
-          idx = idx >= L ? idx - L : (idx < 0 ? idx + L : idx);
-        }
-#pragma unroll
-        for (int pol = 0; pol < 4; ++pol) res[r][pol] = acc[pol];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < PPT; ++r)
-#pragma unroll
-        for (int pol = 0; pol < 4; ++pol) sg[pol * NPIX + tid + r * NT] = res[r][pol];
-      __syncthreads();
-    }
   }
 }
 
@@ -321,7 +329,8 @@ __device__ __forceinline__ void lds_centred_dft_one_thread_per_line(float2 *sg, 
   using Lay = SgLayout<L>;
   constexpr int NPIX = L * L, PPT = NPIX / NT, H = L / 2;
   const int tid = threadIdx.x;
-  if constexpr (Lay::FFT) {
+  static_assert(Lay::FFT, "subgrid transform: L = 2^n or 3 x 2^n");
+  {
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
       for (int line = tid; line < 4 * L; line += NT) {
@@ -339,44 +348,6 @@ __device__ __forceinline__ void lds_centred_dft_one_thread_per_line(float2 *sg, 
 #pragma unroll
         for (int k = 0; k < L; ++k) base[k * step] = (k & 1) ? make_float2(-x[k].x, -x[k].y) : x[k];
       }
-      __syncthreads();
-    }
-  } else {
-    const float sgn = INV ? -1.0f : 1.0f;
-#pragma unroll 1
-    for (int pass = 0; pass < 2; ++pass) {
-      float2 res[PPT][4];
-#pragma unroll
-      for (int r = 0; r < PPT; ++r) {
-        const int pix = tid + r * NT;
-        const int row = pix / L, col = pix % L;
-        // pass 0: transform along a row (output column `col`); pass 1: along a column (output row `row`)
-        const int kout = (pass == 0 ? col : row) - H;
-        int idx = (kout * -H) % L;
-        if (idx < 0) idx += L;
-        float2 acc[4] = {};
-#pragma unroll 8
-        for (int q = 0; q < L; ++q) {
-          float2 w = tw[idx];
-          w.y *= sgn;
-          const int src = pass == 0 ? row * L + q : q * L + col;
-#pragma unroll
-          for (int pol = 0; pol < 4; ++pol) {
-            const float2 x = sg[pol * NPIX + src];
-            acc[pol].x += x.x * w.x - x.y * w.y;
-            acc[pol].y += x.x * w.y + x.y * w.x;
-          }
-          idx += kout;
-          idx = idx >= L ? idx - L : (idx < 0 ? idx + L : idx);
-        }
-#pragma unroll
-        for (int pol = 0; pol < 4; ++pol) res[r][pol] = acc[pol];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < PPT; ++r)
-#pragma unroll
-        for (int pol = 0; pol < 4; ++pol) sg[pol * NPIX + tid + r * NT] = res[r][pol];
       __syncthreads();
     }
   }

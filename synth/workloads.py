@@ -18,9 +18,9 @@ Workloads (sizes are the defaults; ``subset`` cuts them down):
 * ``skalow``    512 stations on 3 log-spiral arms to 35 km, 64 x 1 s,
                 16 channels at 50-350 MHz, L = 32, 8192^2 grid at 1",
                 A-terms changing every 32 timesteps, 10 % random flags.
-* ``precision`` the ``lofar`` geometry with a 10 Jy point source at
-                (l, m) = (sin 5 deg, 0), visibilities from the measurement
-                equation in FP64, identity A-terms.
+* ``precision`` the ``lofar`` geometry and A-terms with a 10 Jy point
+                source at (l, m) = (sin 5 deg, 0), visibilities from the
+                measurement equation in FP64 with identity gains.
 
 Nothing here performs any part of image-domain gridding.
 """
@@ -254,14 +254,15 @@ def _lofar(seed, with_vis):
 
 
 def _precision(seed, with_vis):
-    # the station layout and track of ``lofar`` (drawn from that workload's seed);
-    # the data are a point source, so ``seed`` draws nothing here
-    nst, nt, dt, bl, uvw, freqs, meta = _lofar_geometry(np.random.default_rng(SEED_BASE + 2))
+    # the station layout, track and A-terms of ``lofar`` (drawn from that workload's seed, in its
+    # order); the data are a point source with identity gains, so ``seed`` draws nothing here
+    rng = np.random.default_rng(SEED_BASE + 2)
+    nst, nt, dt, bl, uvw, freqs, meta = _lofar_geometry(rng)
     L, N, beta = 32, 4096, 7
     cell = 2.5 * ARCSEC
     aslot = 256
     nslot = -(-nt // aslot)
-    aterms = _identity_aterms(nslot, nst, L)
+    aterms = _near_identity_aterms(rng, nslot, nst, L)
     src = (np.sin(np.deg2rad(5.0)), 0.0)
     vis = _point_source_vis(uvw, freqs, src[0], src[1], 10.0) if with_vis else None
     meta.update(cell=cell, source_lm=src, flux=10.0)

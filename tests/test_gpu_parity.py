@@ -65,11 +65,18 @@ def _case(name):
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("stage", [0, 1])
-def test_gridder_subgrids(gpu, name, stage):
+@pytest.mark.parametrize("path", ["auto", "direct"])
+def test_gridder_subgrids(gpu, name, stage, path):
     torch, idg = gpu
     wl, oplan = _case(name)
-    say(f"[gridder stage {stage}] case={name} subgrids={oplan.nr_subgrids}")
+    if path == "direct" and wl.subgrid_size != 32:
+        pytest.skip("only 32 x 32 subgrids have a second sum path")
+    say(f"[gridder stage {stage}] case={name} path={path} subgrids={oplan.nr_subgrids}")
     plan = idg.Plan.from_workload(wl)
+    plan.set_tuning(sum_path=path)
+    if path == "auto" and wl.subgrid_size == 32:
+        sp = plan.sum_paths()
+        assert sp["separable0"][0] + sp["separable1"][0] > 0      # the separable form is what is checked here
     d = to_dev(wl)
     L = wl.subgrid_size
     P = plan.nr_subgrids

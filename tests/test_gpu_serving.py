@@ -78,3 +78,69 @@ def test_admission_refuses_oversized_job_and_isolates_failures(env):
         futs[2].result()
     for f in (futs[0], futs[3], futs[4]):
         assert f.result() is not None
+
+
+def _digest(torch, out):
+    """Bitwise digest of a complex64 tensor: weighted int64 sums of its 8-byte words (mod 2^64)."""
+    x = out.reshape(-1).view(torch.int64)
+    n = x.numel()
+    m = n - n % 64
+    w = torch.tensor([(0x9E3779B97F4A7C15 * (i + 1)) % (1 << 61) + 1 for i in range(64)], dtype=torch.int64,
+                     device=x.device)
+    a = x[:m].view(-1, 64)
+    rows = a.sum(1)
+    idx = torch.arange(rows.numel(), dtype=torch.int64, device=x.device) * 2654435761 + 1
+    return torch.stack([(a * w).sum(), (rows * idx).sum(), (x[m:] * w[:n - m]).sum()])
+
+
+class _DigestJob:
+    """A serving job whose output is replaced by its digest on the job's own stream."""
+
+    def __init__(self, torch, job):
+        self.__dict__.update(job.__dict__)
+        self._torch, self._job = torch, job
+
+    def launch(self, stream):
+        out = self._job.launch(stream)
+        with self._torch.cuda.stream(stream):
+            return _digest(self._torch, out)
+
+
+def test_full_trace_results_alone_equal_results_in_the_mix():
+    # the serving benchmark's 400-job trace (8-station and LOFAR-like classes, full datasets), replayed with
+    # 4 slots in the persistent form; every job's output must equal, bit for bit, that of the job run alone
+    require_gpu()
+    import torch
+    from paper_1909_07226_amd import serve
+    tiny = synth.make_workload("tiny", nt=2048, nch=16)
+    lofar = synth.make_workload("lofar")
+    dev = "cuda"
+
+    def to_dev(wl):
+        return dict(uvw=torch.from_numpy(wl.uvw).to(dev), freqs=torch.from_numpy(wl.freqs).to(dev),
+                    vis=torch.from_numpy(wl.vis).to(dev), aterms=torch.from_numpy(wl.aterms).to(dev),
+                    taper=torch.from_numpy(wl.taper).to(dev))
+
+    g = torch.Generator(device=dev).manual_seed(11)
+    grids = {c: torch.complex(torch.randn((4, n, n), generator=g, device=dev),
+                              torch.randn((4, n, n), generator=g, device=dev)).to(torch.complex64)
+             for c, n in (("tiny", tiny.grid_size), ("lofar", lofar.grid_size))}
+    trace = synth.serving_trace(n_jobs=400)
+    jobs, templates = serve.jobs_from_trace(trace, {"tiny": tiny, "lofar": lofar},
+                                            {"tiny": to_dev(tiny), "lofar": to_dev(lofar)}, grids)
+    say(f"[serving invariance, full trace] {len(jobs)} jobs, {len(templates)} plans")
+    djobs = [_DigestJob(torch, j) for j in jobs]
+    for tp in templates.values():
+        tp["plan"].set_tuning(form="persistent")
+    with serve.Server(slots=4, mem_budget=48 << 30) as srv:
+        futs = serve.replay(srv, djobs, trace["arrivals"] * 0.05)     # 20x the trace's rate: jobs overlap
+    mixed = [f.result().cpu() for f in futs]
+    summ = serve.latency_summary(futs)
+    say(f"    mix: {summ}")
+    assert summ["jobs"] == len(jobs)
+    for tp in templates.values():
+        tp["plan"].set_tuning(form="plain")
+    stream = torch.cuda.current_stream()
+    for job, dj, res in zip(jobs, djobs, mixed):
+        alone = dj.launch(stream).cpu()
+        assert torch.equal(alone, res), job.name
