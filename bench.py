@@ -33,7 +33,9 @@ per launch over the launch time, against the dense fp16 peak (the fp16
 high/low operand parts that give 22-bit operands execute 3x the order-0
 products; "executed" reports that rate).  "direct_equivalent" divides the
 method's operation count above by the same time, against the FP32 vector
-peak: the rate a direct-sum kernel would need to match it.  Launch times come
+peak: the rate a direct-sum kernel would need to match it.  "frac_of_measured"
+divides by the rate this device sustains for that instruction kind instead
+(idg_device_rates microkernels, reported under "device_rates").  Launch times come
 from HIP events recorded by the library on the launching stream.  "roofline"
 is for the dominant (longer) of the two kernels; both are reported.  The CPU
 baseline is the float64 oracle on a bounded sample, timed on this host.
@@ -123,6 +125,20 @@ def kernel_roofline(flops_direct, paths, L, launch_ms, launches):
         out.update(bound="alu", achieved=round(direct, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                    frac=round(direct / FP32_PEAK_TFLOPS, 4), flop_per_launch=flops_direct / launches)
     return out
+
+
+def add_measured_fracs(r, rates):
+    """Fractions of the rates this device sustains (idg_device_rates) beside those of its published peaks."""
+    if not rates or not r:
+        return r
+    fp32, mfma = rates["fp32_fma_tflops"], rates["fp16_mfma_tflops"]
+    r["frac_of_measured"] = round(r["achieved"] / (mfma if r["bound"] == "mfma" else fp32), 5)
+    if "executed" in r:
+        r["executed"]["frac_of_measured"] = round(r["executed"]["achieved"] / mfma, 5)
+    if "direct_equivalent" in r:
+        de = r["direct_equivalent"]
+        de["frac_of_measured"] = round(de["achieved"] / fp32, 4)
+    return r
 
 
 def hbm_record_path(workload):
@@ -341,8 +357,8 @@ def hbm_stages(idg, torch, plan, grid, stream, adder_ms_per_step, log, max_subgr
 
 
 def serving_leg(lofar_wl, lofar_dev, n_jobs, log):
-    """Replay one request trace twice: continuous batching (4 slots, persistent form) and a FIFO
-    (1 slot, plain form).  p50/p99 of completion - arrival."""
+    """Replay one request trace under continuous batching (4 slots; persistent and plain forms) and a
+    FIFO (1 slot, plain form), at the trace's rate and saturated.  p50/p99 of completion - arrival."""
     import torch
     import synth
     from paper_1909_07226_amd import serve
@@ -369,15 +385,20 @@ def serving_leg(lofar_wl, lofar_dev, n_jobs, log):
                           grid=grids[cls])
             j.launch(torch.cuda.current_stream())
     torch.cuda.synchronize()
-    for label, slots, form in (("continuous", 4, "persistent"), ("fifo_plain", 1, "plain")):
-        for tp in templates.values():
-            tp["plan"].set_tuning(form=form)
-        with serve.Server(slots=slots, mem_budget=48 << 30) as srv:
-            futs = serve.replay(srv, jobs, trace["arrivals"])
-        summ = serve.latency_summary(futs)
-        summ.update(slots=slots, form=form, failed=sum(1 for f in futs if f._error is not None))
-        out[label] = summ
-        log(f"[bench] serving {label}: {summ}")
+    # at the trace's rate, and with the arrivals compressed 50x (2500 jobs/s offered: more than the GPU
+    # completes, so the queue never drains and the schedule decides the throughput)
+    for rate_label, scale in (("", 1.0), ("saturated_", 0.02)):
+        for label, slots, form in (("continuous", 4, "persistent"), ("continuous_plain", 4, "plain"),
+                                   ("fifo_plain", 1, "plain")):
+            for tp in templates.values():
+                tp["plan"].set_tuning(form=form)
+            with serve.Server(slots=slots, mem_budget=48 << 30) as srv:
+                futs = serve.replay(srv, jobs, trace["arrivals"] * scale)
+            summ = serve.latency_summary(futs)
+            summ.update(slots=slots, form=form, offered_jobs_per_s=round(len(jobs) / (trace["arrivals"][-1] * scale), 1),
+                        failed=sum(1 for f in futs if f._error is not None))
+            out[rate_label + label] = summ
+            log(f"[bench] serving {rate_label + label}: {summ}")
     return out
 
 
@@ -512,7 +533,9 @@ class Leg:
         """Set the plan's schedule: autotuned (args.form == "auto") or as given.  Returns autotune info."""
         plan = self.plan
         tune_info = None
-        if args.form == "auto":
+        if args.tuning:
+            plan.set_tuning(**json.loads(args.tuning))
+        elif args.form == "auto":
             from paper_1909_07226_amd.autotune import autotune
             self.log(f"[bench] {self.name}: autotuning the schedule (outside the timed region)")
             tune_info = autotune(plan, self.uvw, self.freqs, self.vis, self.aterms, self.taper, self.grid,
@@ -589,7 +612,7 @@ def run_leg(idg, torch, name, args, log, compare_plain=True):
     res["plan_ms"] = round(leg.plan_ms, 1)
     res["autotune_ms"] = tune_info["timings_ms"] if tune_info else None
     res["plain_form"] = None
-    if compare_plain and args.form == "auto":
+    if compare_plain and args.form == "auto" and not args.tuning:
         tuned = leg.plan.get_tuning()
         # the plain form with the same degridder shape and adder chunk: only the launch form differs
         leg.plan.set_tuning(form="plain", blocks_per_cu=0, adder_chunk=tuned["adder_chunk"],
@@ -622,6 +645,8 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent form: workgroups per CU (0 = max)")
     ap.add_argument("--degrid-shape", default="standard", choices=("standard", "wide"),
                     help="degridder task shape when --form is given (autotuned otherwise)")
+    ap.add_argument("--tuning", default="", metavar="JSON",
+                    help="the plan's whole schedule as idg Plan.get_tuning() returns it (overrides --form)")
     ap.add_argument("--sum-path", default="auto", choices=("auto", "direct"),
                     help="with --form plain/persistent: separable form where it applies, or the direct sum")
     ap.add_argument("--adder-chunk", type=int, default=0, help="adder: longest tile-list run per workgroup (0 = 256)")
@@ -629,6 +654,8 @@ def main():
                     help="skip the LOFAR-like leg (and the W-layer and serving legs on its geometry)")
     ap.add_argument("--serve-jobs", type=int, default=400, help="jobs in the serving trace (0 = skip serving)")
     ap.add_argument("--no-wstack", action="store_true", help="skip the W-layer leg (wider field, layered plan)")
+    ap.add_argument("--no-device-rates", action="store_true",
+                    help="skip the device-rate microbenchmarks (idg_device_rates)")
     ap.add_argument("--no-hbm-stages", action="store_true", help="skip the standalone HBM-bound stage timings")
     ap.add_argument("--scratch-gb", type=float, default=0.0,
                     help="subgrid scratch budget in GB (0 = enough for the whole plan: one gridder launch)")
@@ -645,8 +672,14 @@ def main():
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a HIP device")
     idg.lib()
+    rates = None
+    if not args.no_device_rates:
+        rates = {k: round(v, 2) for k, v in idg.device_rates().items()}
+        log(f"[bench] device rates: {rates}")
 
     leg, res = run_leg(idg, torch, args.workload, args, log)
+    for key in ("roofline", "gridder_roofline", "degridder_roofline"):
+        add_measured_fracs(res[key], rates)
     result = {
         "metric": "MVis/s grid+degrid, % of FP32 VALU peak; p50/p99 job latency vs plain",
         "value": res["value"],
@@ -664,6 +697,7 @@ def main():
         "config": leg.config(),
         "roofline": res["roofline"],
         "cpu_baseline": None,
+        "device_rates": rates,
     }
     for key in ("gridder_roofline", "degridder_roofline", "grid_mvis_s", "degrid_mvis_s", "kernels_ms_per_step",
                 "plan_ms", "plain_form", "autotune_ms"):
@@ -680,6 +714,8 @@ def main():
         if not args.no_lofar:
             lleg, lres = run_leg(idg, torch, "lofar", args, log)
             lres["config"] = lleg.config()
+            for key in ("roofline", "gridder_roofline", "degridder_roofline"):
+                add_measured_fracs(lres[key], rates)
             result["lofar"] = lres
     if lleg is not None:
         if not args.no_wstack:

@@ -430,6 +430,15 @@ int idg_taper_correction(int32_t L, double max_shift, const double *taper, int32
 int idg_profile(int enable);
 int idg_profile_read(double *ms, int64_t *launches, int reset);
 
+/* Measurement aid, not part of the method: the rates this device sustains for
+ * the instruction kinds the gridder and degridder issue, from microkernels
+ * (8 workgroups per compute unit, best of 3 launches) on the current device:
+ * float32 multiply-add flop/s (2 flop each), sine / cosine wave64
+ * instructions/s, and fp16 matrix-core flop/s (32 x 32 x 16 products).
+ * Synchronous; allocates a small device buffer.  Any pointer may not be NULL.
+ * Errors: IDG_EINVAL (NULL pointer), IDG_EHIP. */
+int idg_device_rates(double *fp32_fma_flops, double *sincos_instr, double *fp16_mfma_flops);
+
 /* Wait for `stream` and report any error its queued work raised. */
 int idg_sync(void *stream);
 

@@ -29,6 +29,7 @@ from ._lib import (  # noqa: F401
     lib,
     profile,
     profile_read,
+    device_rates,
     split_subgrids,
     subgrid_fft,
     sync,

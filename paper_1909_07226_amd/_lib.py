@@ -25,7 +25,7 @@ EXPORTED = ("idg_plan", "idg_plan_stats", "idg_plan_export", "idg_plan_destroy",
             "idg_last_error", "idg_version", "idg_profile", "idg_profile_read", "idg_plan_set_tuning",
             "idg_plan_get_tuning", "idg_grid_to_image", "idg_image_to_grid", "idg_taper_optimal",
             "idg_taper_correction", "idg_plan_wlayers", "idg_wstack_to_image", "idg_image_to_wstack",
-            "idg_grid_noalloc", "idg_plan_sum_paths")
+            "idg_grid_noalloc", "idg_plan_sum_paths", "idg_device_rates")
 NOALLOC_SCRATCH_BYTES = 128 << 20          # IDG_NOALLOC_SCRATCH_BYTES
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 DEGRID_STANDARD, DEGRID_WIDE = 0, 1
@@ -99,6 +99,7 @@ def lib():
         L.idg_taper_correction.argtypes = [i32, ctypes.c_double, vp, i32, vp]
         L.idg_plan_wlayers.argtypes = [vp, vp, vp]
         L.idg_plan_sum_paths.argtypes = [vp, vp, vp]
+        L.idg_device_rates.argtypes = [vp, vp, vp]
         L.idg_wstack_to_image.argtypes = [vp, i32, vp, i32, ctypes.c_double, vp, vp, vp, vp]
         L.idg_image_to_wstack.argtypes = [vp, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp]
         for name in EXPORTED:
@@ -435,6 +436,14 @@ def version():
 def profile(enable=True):
     """Turn the library's per-stage HIP-event timing on or off (idg_profile)."""
     check(lib().idg_profile(1 if enable else 0))
+
+
+def device_rates():
+    """idg_device_rates: {"fp32_fma_tflops", "sincos_ginstr_per_s", "fp16_mfma_tflops"} on the current device."""
+    v = [ctypes.c_double() for _ in range(3)]
+    check(lib().idg_device_rates(*[ctypes.byref(x) for x in v]))
+    return {"fp32_fma_tflops": v[0].value / 1e12, "sincos_ginstr_per_s": v[1].value / 1e9,
+            "fp16_mfma_tflops": v[2].value / 1e12}
 
 
 def profile_read(reset=True):

@@ -90,7 +90,7 @@ def build_sanitized(verbose=False):
     xhost = [f for flag in SAN_HOST for f in ("-Xarch_host", flag)]
     hip_flags = [f for f in HIP_FLAGS if f != "-O3"] + ["-O1", "--offload-host-only"] + xhost
     host_flags = [f for f in CXX_FLAGS if f != "-O2"] + ["-O1"] + SAN_HOST
-    kernel_objs = [os.path.join(BUILD, src.replace(".", "_") + ".o") for src in ("kernels.hip", "image.hip")]
+    kernel_objs = [os.path.join(BUILD, src.replace(".", "_") + ".o") for src in ("kernels.hip", "image.hip", "calib.hip")]
     missing = [o for o in kernel_objs if not os.path.exists(o)]
     if missing:
         raise RuntimeError(f"sanitizer build: run the plain build first ({', '.join(missing)} missing)")
@@ -113,7 +113,7 @@ def build(verbose=False):
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
     objs = []
-    for src, lang in (("kernels.hip", "hip"), ("image.hip", "hip"), ("api.cpp", "hip")):
+    for src, lang in (("kernels.hip", "hip"), ("image.hip", "hip"), ("calib.hip", "hip"), ("api.cpp", "hip")):
         obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
         _run([hipcc, "-x", lang, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)

@@ -1229,6 +1229,12 @@ int idg_profile_read(double *ms, int64_t *launches, int reset) {
   return IDG_OK;
 }
 
+int idg_device_rates(double *fp32_fma_flops, double *sincos_instr, double *fp16_mfma_flops) {
+  if (!fp32_fma_flops || !sincos_instr || !fp16_mfma_flops) return fail(IDG_EINVAL, "idg_device_rates: NULL pointer");
+  HIP_TRY(idg::measure_device_rates(fp32_fma_flops, sincos_instr, fp16_mfma_flops), "idg_device_rates");
+  return IDG_OK;
+}
+
 int idg_sync(void *stream) {
   HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)), "idg_sync");
   HIP_TRY(hipGetLastError(), "idg_sync");

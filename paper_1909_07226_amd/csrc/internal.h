@@ -115,6 +115,10 @@ hipError_t launch_zero_samples(const int64_t *ids, int64_t n, float2 *vis, hipSt
 constexpr size_t kNoAllocScratchBytes = size_t(IDG_NOALLOC_SCRATCH_BYTES);
 hipError_t noalloc_scratch(void **out);
 
+// Device rates (calib.hip): float32 multiply-add flop/s, sine / cosine wave-instructions/s, fp16 matrix-core
+// flop/s, each from microkernels over 8 workgroups per compute unit on the current device (synchronous).
+hipError_t measure_device_rates(double *fma_flops, double *sincos_instr, double *mfma_flops);
+
 // master grid <-> image (image.hip)
 bool image_size_supported(int N);
 hipError_t launch_image_twiddles(float2 *tw, int N, hipStream_t s);

@@ -824,13 +824,10 @@ __device__ __forceinline__ void grid_one_mfma(const KernelArgs &a, int local, Gr
       yexp = e;
     }
     const float yinv = ldexpf(1.0f, -yexp);
-    SepOps cur;
-    sep_operands(s_u, s_v, s_w, s_yr, s_yi, kh, xa, yinv, winv, order1, cur);
     for (int kb = 0; kb < nkp; kb += 16) {
-      SepOps nxt;
-      sep_mfma(cur, order1, gr, gi);
-      if (kb + 16 < nkp) sep_operands(s_u, s_v, s_w, s_yr, s_yi, kb + 16 + kh, xa, yinv, winv, order1, nxt);
-      cur = nxt;
+      SepOps o;
+      sep_operands(s_u, s_v, s_w, s_yr, s_yi, kb + kh, xa, yinv, winv, order1, o);
+      sep_mfma(o, order1, gr, gi);
     }
     __syncthreads();  // staging and sm.ybits are reused by the next round
   }
@@ -857,14 +854,19 @@ __device__ __forceinline__ void grid_one_mfma(const KernelArgs &a, int local, Gr
   grid_finish<L>(a, d, local, acc, s_sg, sm.tw);
 }
 
+// Held to 3 waves per SIMD (144 VGPRs, no spills): three workgroups per compute unit hide the staging
+// loads, barriers and epilogue of one subgrid behind the others; measured 20 % faster than the 2 waves the
+// compiler picks by itself (on the SKA-low-like share, 58.8 -> 46.9 ms).  4 waves spill 57 VGPRs and lose.
 template <int L>
-__global__ void __launch_bounds__(Cfg<L>::NT) gridder_mfma_kernel(KernelArgs a, const int32_t *order) {
+__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(3)))
+gridder_mfma_kernel(KernelArgs a, const int32_t *order) {
   __shared__ GridderSmem<L> sm;
   if (threadIdx.x < L) sm.tw[threadIdx.x] = a.twiddle[threadIdx.x];
   grid_one_mfma<L>(a, order[blockIdx.x], sm);
 }
 
-// Held to 2 waves per SIMD (the one-subgrid form's budget); the loop would otherwise take 1.
+// Held to 2 waves per SIMD; the loop would otherwise take 1.  At 3 waves it measured slower (SKA-low-like
+// share: 63.7 against 54.8 ms).
 template <int L>
 __global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(2)))
 gridder_mfma_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_head) {
@@ -892,12 +894,15 @@ constexpr int kDegridSmallK = 128;  // subgrids with at most this many visibilit
 constexpr int kDegridSmallNB = 4;  // visibilities per cross-lane reduction
 
 
-template <int L>
+template <int L, bool SEP = false>
 struct DegridderSmem {
   static constexpr bool LMN_LDS = L <= 24;  // larger subgrids read the pixel coordinates through the cache
-  // the small-subgrid path reuses sg for its staged offsets and per-wave sums (float2 units)
+  // the small-subgrid path reuses sg for its staged offsets and per-wave sums (float2 units); the separable
+  // kernels (SEP) for their staged offsets, outputs and phasor tables
   static constexpr int SMALL = (2 * kDegridSmallK * 16 + (Cfg<L>::NT / 64) * kDegridSmallK * 32) / 8;
-  static constexpr int SG = SgLayout<L>::SIZE > SMALL ? SgLayout<L>::SIZE : SMALL;
+  static constexpr int SEPT = SEP ? 41728 / 8 : 0;
+  static constexpr int SG0 = SgLayout<L>::SIZE > SMALL ? SgLayout<L>::SIZE : SMALL;
+  static constexpr int SG = SG0 > SEPT ? SG0 : SEPT;
   float2 sg[SG];                            // SgLayout<L>, then [NPIX][4] after the A-terms
   float4 lmn[LMN_LDS ? L * L : 1];
   float2 tw[L];
@@ -1242,11 +1247,11 @@ __device__ __forceinline__ void degrid_small(const KernelArgs &a, const DevSubgr
 // high/low parts, scaled by a power of two), B = conj(U) of 32 samples (lane l: sample l % 32); then every lane
 // forms conj(V_k(j)) for the 16 rows j of its accumulators and the two half-waves add their dot products.
 // b: this thread's pixels (tid + r NT) after the A-terms and taper; sm.sg is free and sm.ybits zero on entry.
-template <int L>
+template <int L, class SM>
 __device__ __forceinline__ void degrid_sep(const KernelArgs &a, const DevSubgrid &d, const float2 (&b)[4][4],
-                                           DegridderSmem<L> &sm, double u0, double v0) {
+                                           SM &sm, double u0, double v0) {
   static_assert(L == 32 && Cfg<L>::NT == 256, "the matrix-core degridder runs 32 x 32 subgrids on four waves");
-  constexpr int NT = Cfg<L>::NT, PPT = 4, CH = 256;
+  constexpr int NT = Cfg<L>::NT, PPT = 4, CH = 64;
   const int tid = threadIdx.x, lane = tid & 63, pol = tid >> 6, hw = lane >> 5, col = lane & 31;
   const bool order1 = d.order >= 1;
   const int K = d.nvis;
@@ -1292,10 +1297,21 @@ __device__ __forceinline__ void degrid_sep(const KernelArgs &a, const DevSubgrid
       }
     }
   }
-  __syncthreads();  // sm.sg holds the staged samples below
+  __syncthreads();  // sm.sg holds the staged samples and the phasor tables below
+  // Per staging round of CH samples (k < nkp, a multiple of 32), in LDS: du, dv, dw; the outputs [4 pols][2];
+  // V_k(j) in float32 (real and imaginary planes [CH][kDegVS]); U_k(i) as fp16 high and low parts of its real
+  // and imaginary parts (planes [CH][kDegUS]).  The phasors do not depend on the polarisation: the four waves
+  // build them once per round.  Rows are padded by 16 bytes against LDS bank conflicts.
+  constexpr int kDegVS = L + 4, kDegUS = L + 8;
   float *s_u = reinterpret_cast<float *>(sm.sg), *s_v = s_u + CH, *s_w = s_u + 2 * CH;
   float *s_out = s_u + 3 * CH;  // [4 pols][2][CH]
+  float *t_vr = s_out + 8 * CH, *t_vi = t_vr + CH * kDegVS;
+  _Float16 *t_urh = reinterpret_cast<_Float16 *>(t_vi + CH * kDegVS), *t_url = t_urh + CH * kDegUS;
+  _Float16 *t_uih = t_url + CH * kDegUS, *t_uil = t_uih + CH * kDegUS;
+  static_assert((11 * CH + 2 * CH * kDegVS) * 4 + 4 * CH * kDegUS * 2 <= int(sizeof(sm.sg)), "room for the tables");
   const float bsc = ldexpf(1.0f, bexp), twopi = 6.283185307179586f;
+  const int fq = tid & 31, fk = tid >> 5;   // table fill: row q of samples fk + 8 m
+  const float2 fxa = sm.sep[fq];
   for (int k0 = 0; k0 < K; k0 += CH) {
     const int nk = min(CH, K - k0), nkp = (nk + 31) & ~31;
     if (tid < nkp) {
@@ -1314,26 +1330,35 @@ __device__ __forceinline__ void degrid_sep(const KernelArgs &a, const DevSubgrid
       s_w[tid] = dw;
     }
     __syncthreads();
+    for (int k = fk; k < nkp; k += 8) {
+      const float du = s_u[k], dv = s_v[k], dw = s_w[k];
+      const float pu = __builtin_amdgcn_fractf(du * fxa.x + dw * fxa.y);
+      const float pv = __builtin_amdgcn_fractf(dv * fxa.x + dw * fxa.y);
+      t_vr[k * kDegVS + fq] = __builtin_amdgcn_cosf(pv);
+      t_vi[k * kDegVS + fq] = __builtin_amdgcn_sinf(pv);
+      const float ur = __builtin_amdgcn_cosf(pu), ui = __builtin_amdgcn_sinf(pu);
+      const auto h = __builtin_amdgcn_cvt_pkrtz(ur, ui);
+      const auto l = __builtin_amdgcn_cvt_pkrtz(ur - float(h[0]), ui - float(h[1]));
+      t_urh[k * kDegUS + fq] = h[0];
+      t_uih[k * kDegUS + fq] = h[1];
+      t_url[k * kDegUS + fq] = l[0];
+      t_uil[k * kDegUS + fq] = l[1];
+    }
+    __syncthreads();
     for (int kb = 0; kb < nkp; kb += 32) {
       const int k = kb + col;  // this lane's sample
-      const float du = s_u[k], dv = s_v[k], dw = s_w[k];
+      const float dw = s_w[k];
       floatx16 t0r, t0i, t1r, t1i;
 #pragma unroll
       for (int e = 0; e < 16; ++e) t0r[e] = t0i[e] = t1r[e] = t1i[e] = 0.0f;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         // conj(U_k(i)) = Ur - i Ui for i = 16 q + 8 hw + s
-        float ur[8], ui[8];
-#pragma unroll
-        for (int s8 = 0; s8 < 8; ++s8) {
-          const float2 xa = sm.sep[16 * q + 8 * hw + s8];
-          const float pu = __builtin_amdgcn_fractf(du * xa.x + dw * xa.y);
-          ur[s8] = __builtin_amdgcn_cosf(pu);
-          ui[s8] = __builtin_amdgcn_sinf(pu);
-        }
-        half8 urh, url, uih, uil;
-        split_half8(ur, urh, url);
-        split_half8(ui, uih, uil);
+        const int o = k * kDegUS + 16 * q + 8 * hw;
+        const half8 urh = *reinterpret_cast<const half8 *>(t_urh + o);
+        const half8 url = *reinterpret_cast<const half8 *>(t_url + o);
+        const half8 uih = *reinterpret_cast<const half8 *>(t_uih + o);
+        const half8 uil = *reinterpret_cast<const half8 *>(t_uil + o);
         const half8 nuih = -uih, nuil = -uil;
         // T_0r += Br Ur + Bi Ui,  T_0i += Bi Ur - Br Ui
         t0r = mfma_split(arh[q], arl[q], urh, url, t0r);
@@ -1351,18 +1376,23 @@ __device__ __forceinline__ void degrid_sep(const KernelArgs &a, const DevSubgrid
       float yr = 0.0f, yi = 0.0f;
       const float w2 = twopi * dw;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int j = 8 * (e >> 2) + 4 * hw + (e & 3);
-        const float2 xa = sm.sep[j];
-        const float pv = __builtin_amdgcn_fractf(dv * xa.x + dw * xa.y);
-        const float vr = __builtin_amdgcn_cosf(pv), vi = __builtin_amdgcn_sinf(pv);
-        float tr = t0r[e], ti = t0i[e];
-        if (order1) {
-          tr = __builtin_fmaf(w2, t1i[e], tr);
-          ti = __builtin_fmaf(-w2, t1r[e], ti);
+      for (int g = 0; g < 4; ++g) {
+        // rows j = 8 g + 4 hw + (0 .. 3): accumulator elements e = 4 g .. 4 g + 3
+        const float4 vr4 = *reinterpret_cast<const float4 *>(t_vr + k * kDegVS + 8 * g + 4 * hw);
+        const float4 vi4 = *reinterpret_cast<const float4 *>(t_vi + k * kDegVS + 8 * g + 4 * hw);
+        const float vrs[4] = {vr4.x, vr4.y, vr4.z, vr4.w}, vis[4] = {vi4.x, vi4.y, vi4.z, vi4.w};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = 4 * g + r;
+          const float vr = vrs[r], vi = vis[r];
+          float tr = t0r[e], ti = t0i[e];
+          if (order1) {
+            tr = __builtin_fmaf(w2, t1i[e], tr);
+            ti = __builtin_fmaf(-w2, t1r[e], ti);
+          }
+          yr = __builtin_fmaf(vr, tr, __builtin_fmaf(vi, ti, yr));
+          yi = __builtin_fmaf(vr, ti, __builtin_fmaf(-vi, tr, yi));
         }
-        yr = __builtin_fmaf(vr, tr, __builtin_fmaf(vi, ti, yr));
-        yi = __builtin_fmaf(vr, ti, __builtin_fmaf(-vi, tr, yi));
       }
       yr += __shfl_xor(yr, 32);
       yi += __shfl_xor(yi, 32);
@@ -1391,8 +1421,8 @@ __device__ __forceinline__ void degrid_sep(const KernelArgs &a, const DevSubgrid
 constexpr int kPathLarge = 0, kPathSmall = 1, kPathSep = 2;  // degridder kernels: visibility-per-lane tasks,
                                                               // pixel-per-lane sums, separable form
 
-template <int L, bool FP32_PHASE, bool WIDE, int PATH>
-__device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, DegridderSmem<L> &sm) {
+template <int L, bool FP32_PHASE, bool WIDE, int PATH, class SM>
+__device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, SM &sm) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L, PPT = NPIX / NT, W = NT / 64;
   constexpr bool SMALL = PATH == kPathSmall;
   const int tid = threadIdx.x;
@@ -1512,12 +1542,12 @@ __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, Degri
   }
 }
 
-template <int L>
-__device__ __forceinline__ void degrid_load_tables(const KernelArgs &a, DegridderSmem<L> &sm) {
+template <int L, class SM>
+__device__ __forceinline__ void degrid_load_tables(const KernelArgs &a, SM &sm) {
   constexpr int NT = Cfg<L>::NT, NPIX = L * L;
   if (threadIdx.x < L) sm.tw[threadIdx.x] = a.twiddle[threadIdx.x];
   if (threadIdx.x < L && a.sep) sm.sep[threadIdx.x] = a.sep[threadIdx.x];
-  if (DegridderSmem<L>::LMN_LDS)
+  if (SM::LMN_LDS)
     for (int pix = threadIdx.x; pix < NPIX; pix += NT) sm.lmn[pix] = a.lmn[pix];
 }
 
@@ -1549,17 +1579,20 @@ degridder_small_kernel(KernelArgs a, const int32_t *order) {
   degrid_one<L, FP32_PHASE, false, kPathSmall>(a, order[blockIdx.x], sm);
 }
 
+// Held to 3 waves per SIMD (154 VGPRs, no spills; 3 x 48 KiB of LDS per compute unit): measured 20 % faster
+// than 2 waves (SKA-low-like share, 49.2 -> 39.1 ms).
 template <int L>
-__global__ void __launch_bounds__(Cfg<L>::NT) degridder_sep_kernel(KernelArgs a, const int32_t *order) {
-  __shared__ DegridderSmem<L> sm;
+__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(3)))
+degridder_sep_kernel(KernelArgs a, const int32_t *order) {
+  __shared__ DegridderSmem<L, true> sm;
   degrid_load_tables<L>(a, sm);
   degrid_one<L, false, false, kPathSep>(a, order[blockIdx.x], sm);
 }
 
 template <int L>
-__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu(3)))
 degridder_sep_persistent_kernel(KernelArgs a, const int32_t *order, int32_t *queue_head) {
-  __shared__ DegridderSmem<L> sm;
+  __shared__ DegridderSmem<L, true> sm;
   degrid_load_tables<L>(a, sm);
   for (;;) {
     if (threadIdx.x == 0) sm.next = atomicAdd(queue_head, 1);

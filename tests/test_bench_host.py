@@ -107,3 +107,14 @@ def test_host_cores_reports_affinity_and_model():
 def test_image_passes():
     assert bench.image_passes(512) == 2 and bench.image_passes(1024) == 2
     assert bench.image_passes(2048) == 3 and bench.image_passes(8192) == 3
+
+
+def test_measured_fractions():
+    rates = {"fp32_fma_tflops": 125.0, "sincos_ginstr_per_s": 280.0, "fp16_mfma_tflops": 2000.0}
+    paths = {"separable0": (10, 1000), "separable1": (10, 1000), "direct": (0, 0)}
+    r = bench.kernel_roofline(1e12, paths, 32, launch_ms=2.0, launches=1)
+    bench.add_measured_fracs(r, rates)
+    assert r["frac_of_measured"] == round(r["achieved"] / 2000.0, 5)
+    assert r["executed"]["frac_of_measured"] == round(r["executed"]["achieved"] / 2000.0, 5)
+    assert r["direct_equivalent"]["frac_of_measured"] == round(500.0 / 125.0, 4)
+    assert bench.add_measured_fracs(dict(r), None) == r      # no rates: unchanged

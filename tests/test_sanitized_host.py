@@ -27,7 +27,7 @@ def _toolchain_or_skip():
         build.asan_runtime()
     except RuntimeError as e:
         pytest.skip(str(e))
-    for src in ("kernels.hip", "image.hip"):
+    for src in ("kernels.hip", "image.hip", "calib.hip"):
         if not os.path.exists(os.path.join(build.BUILD, src.replace(".", "_") + ".o")):
             pytest.skip("plain build objects missing (run the plain build first)")
 
