@@ -392,11 +392,13 @@ def serving_leg(lofar_wl, lofar_dev, n_jobs, log):
                                    ("fifo_plain", 1, "plain")):
             for tp in templates.values():
                 tp["plan"].set_tuning(form=form)
-            with serve.Server(slots=slots, mem_budget=48 << 30) as srv:
+            with serve.Server(slots=slots, mem_budget=48 << 30, keep_results=False) as srv:
                 futs = serve.replay(srv, jobs, trace["arrivals"] * scale)
             summ = serve.latency_summary(futs)
-            summ.update(slots=slots, form=form, offered_jobs_per_s=round(len(jobs) / (trace["arrivals"][-1] * scale), 1),
-                        failed=sum(1 for f in futs if f._error is not None))
+            errors = sorted({f"{type(f._error).__name__}: {f._error}"[:200] for f in futs if f._error is not None})
+            summ.update(slots=slots, form=form,
+                        offered_jobs_per_s=round(float(len(jobs) / (trace["arrivals"][-1] * scale)), 1),
+                        failed=sum(1 for f in futs if f._error is not None), errors=errors[:3])
             out[rate_label + label] = summ
             log(f"[bench] serving {rate_label + label}: {summ}")
     return out
@@ -711,6 +713,7 @@ def main():
         lleg = leg
     else:
         leg.release()
+        idg.trim_scratch()
         if not args.no_lofar:
             lleg, lres = run_leg(idg, torch, "lofar", args, log)
             lres["config"] = lleg.config()
@@ -721,6 +724,7 @@ def main():
         if not args.no_wstack:
             result["wstack"] = wstack_leg(idg, torch, lleg.wl, lleg.plan.get_tuning(), log)
         if args.serve_jobs > 0:
+            idg.trim_scratch()
             result["serving"] = serving_leg(lleg.wl, lleg.dev_inputs(), args.serve_jobs, log)
         lleg.release()
     if not args.no_cpu_baseline:

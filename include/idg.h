@@ -430,6 +430,16 @@ int idg_taper_correction(int32_t L, double max_shift, const double *taper, int32
 int idg_profile(int enable);
 int idg_profile_read(double *ms, int64_t *launches, int reset);
 
+/* Scratch memory.  idg_grid, idg_degrid and the image steps take their device
+ * scratch stream-ordered from a memory pool the library creates per device
+ * (not the device's default pool).  Freed scratch stays in that pool for the
+ * next call -- up to the largest scratch any call has used (a plan's
+ * params.scratch_bytes plus small work lists) -- so that repeated calls do not
+ * map their scratch again.  idg_trim_scratch waits for the current device and
+ * returns the pool's unused memory to the driver beyond keep_bytes.
+ * Errors: IDG_EHIP. */
+int idg_trim_scratch(uint64_t keep_bytes);
+
 /* Measurement aid, not part of the method: the rates this device sustains for
  * the instruction kinds the gridder and degridder issue, from microkernels
  * (8 workgroups per compute unit, best of 3 launches) on the current device:

@@ -30,6 +30,7 @@ from ._lib import (  # noqa: F401
     profile,
     profile_read,
     device_rates,
+    trim_scratch,
     split_subgrids,
     subgrid_fft,
     sync,

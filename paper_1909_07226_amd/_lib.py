@@ -25,7 +25,8 @@ EXPORTED = ("idg_plan", "idg_plan_stats", "idg_plan_export", "idg_plan_destroy",
             "idg_last_error", "idg_version", "idg_profile", "idg_profile_read", "idg_plan_set_tuning",
             "idg_plan_get_tuning", "idg_grid_to_image", "idg_image_to_grid", "idg_taper_optimal",
             "idg_taper_correction", "idg_plan_wlayers", "idg_wstack_to_image", "idg_image_to_wstack",
-            "idg_grid_noalloc", "idg_plan_sum_paths", "idg_device_rates")
+            "idg_grid_noalloc", "idg_plan_sum_paths", "idg_device_rates",
+            "idg_trim_scratch")
 NOALLOC_SCRATCH_BYTES = 128 << 20          # IDG_NOALLOC_SCRATCH_BYTES
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 DEGRID_STANDARD, DEGRID_WIDE = 0, 1
@@ -100,6 +101,7 @@ def lib():
         L.idg_plan_wlayers.argtypes = [vp, vp, vp]
         L.idg_plan_sum_paths.argtypes = [vp, vp, vp]
         L.idg_device_rates.argtypes = [vp, vp, vp]
+        L.idg_trim_scratch.argtypes = [ctypes.c_uint64]
         L.idg_wstack_to_image.argtypes = [vp, i32, vp, i32, ctypes.c_double, vp, vp, vp, vp]
         L.idg_image_to_wstack.argtypes = [vp, i32, ctypes.c_double, vp, vp, i32, vp, vp, vp]
         for name in EXPORTED:
@@ -436,6 +438,11 @@ def version():
 def profile(enable=True):
     """Turn the library's per-stage HIP-event timing on or off (idg_profile)."""
     check(lib().idg_profile(1 if enable else 0))
+
+
+def trim_scratch(keep_bytes=0):
+    """idg_trim_scratch: return the library pool's unused scratch beyond keep_bytes (waits for the device)."""
+    check(lib().idg_trim_scratch(int(keep_bytes)))
 
 
 def device_rates():

@@ -290,6 +290,49 @@ void lmn_table(int L, double S, std::vector<float4> &lmn, std::vector<float2> &t
   }
 }
 
+// The library's stream-ordered memory pool of the current device, created on first use.  Every call's
+// scratch comes from it; freed blocks stay in the pool (release threshold: unlimited) so that repeated
+// calls do not remap tens of GB, and idg_trim_scratch hands them back.  Being the library's own pool, it
+// leaves the device's default pool (torch's and other users') as it is.
+hipError_t scratch_pool(hipMemPool_t *out) {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = pools.find(device);
+  if (it != pools.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  hipMemPoolProps props = {};
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = device;
+  hipMemPool_t pool = nullptr;
+  e = hipMemPoolCreate(&pool, &props);
+  if (e != hipSuccess) return e;
+  uint64_t keep = UINT64_MAX;
+  e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  if (e != hipSuccess) {
+    (void)hipMemPoolDestroy(pool);
+    return e;
+  }
+  pools.emplace(device, pool);
+  *out = pool;
+  return hipSuccess;
+}
+
+// Stream-ordered scratch from the library's pool (released with hipFreeAsync).
+hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t s) {
+  hipMemPool_t pool = nullptr;
+  const hipError_t e = scratch_pool(&pool);
+  if (e != hipSuccess) return e;
+  return hipMallocFromPoolAsync(p, bytes, pool, s);
+}
+
 // Device metadata of `plan` on the current device, uploaded on first use.
 int device_plan(idg_plan_t plan, DevPlan **out) {
   int device = 0;
@@ -411,14 +454,6 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
   if ((rc = upload(&dp->items, all_items.data(), all_items.size(), "plan upload (adder)")) != IDG_OK) return rc;
   if ((rc = upload(&dp->combine, all_combine.data(), all_combine.size(), "plan upload (adder)")) != IDG_OK) return rc;
   HIP_TRY(hipDeviceGetAttribute(&dp->nr_cus, hipDeviceAttributeMultiprocessorCount, device), "CU count");
-  // idg_grid takes its scratch from the device's stream-ordered pool on every call; keep freed
-  // blocks in the pool (do not return them to the driver at each synchronisation) so that
-  // repeated calls do not remap tens of GB
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-    uint64_t keep = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-  }
   *out = dp.get();
   plan->dev.emplace(device, std::move(dp));
   return IDG_OK;
@@ -679,7 +714,7 @@ int idg_grid_subgrids(idg_plan_t plan, const double *uvw_d, const double *freqs_
     for (int32_t i = 0; i < n; ++i)
       if (dp->order[size_t(a.first + i)] < 0) ord.push_back(i);
     int32_t *ord_d = nullptr;
-    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&ord_d), ord.size() * sizeof(int32_t), s),
+    HIP_TRY(scratch_alloc(reinterpret_cast<void **>(&ord_d), ord.size() * sizeof(int32_t), s),
             "idg_grid_subgrids: order list");
     hipError_t e = hipMemcpyAsync(ord_d, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host list goes out of scope
@@ -738,7 +773,7 @@ static void carve_grid_scratch(char *base, int64_t slots, GridScratch &g) {
 
 static int alloc_grid_scratch(const DevPlan *dp, int64_t nsub, int L, hipStream_t s, GridScratch &g) {
   char *base = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&base), grid_scratch_bytes(dp, nsub, L), s), "scratch allocation");
+  HIP_TRY(scratch_alloc(reinterpret_cast<void **>(&base), grid_scratch_bytes(dp, nsub, L), s), "scratch allocation");
   carve_grid_scratch(base, dp->max_slots, g);
   return IDG_OK;
 }
@@ -896,7 +931,7 @@ int idg_degrid(idg_plan_t plan, const double *uvw_d, const double *freqs_d, cons
   a.count = int32_t(P);
   if (plan->tuning.degrid_form == IDG_FORM_PERSISTENT) {
     int32_t *counter = nullptr;  // queue counters: large and small subgrids of the direct sum, separable form
-    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&counter), 256, s), "idg_degrid: queue counter");
+    HIP_TRY(scratch_alloc(reinterpret_cast<void **>(&counter), 256, s), "idg_degrid: queue counter");
     hipError_t err;
     {
       StageTimer tm(IDG_STAGE_DEGRIDDER, s);
@@ -967,7 +1002,7 @@ static int image_transform(const char *fn, bool to_image, const idg_cf32 *src_d,
   // twiddles, plus a [4][N][N] intermediate for in-place calls of the four-step form
   const size_t nscr = idg::image_needs_scratch(N, in, out) ? size_t(4) * N * N : 0;
   float2 *tw = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&tw), (size_t(N) / 2 + nscr) * sizeof(float2), s),
+  HIP_TRY(scratch_alloc(reinterpret_cast<void **>(&tw), (size_t(N) / 2 + nscr) * sizeof(float2), s),
           "image scratch");
   float2 *scr = nscr ? tw + N / 2 : nullptr;
   hipError_t e = idg::launch_image_twiddles(tw, N, s);
@@ -1016,7 +1051,7 @@ int idg_wstack_to_image(const idg_cf32 *grids_d, int32_t nr_wlayers, const doubl
   const size_t nn = size_t(4) * N * N;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   float2 *scr = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&scr), (nn + size_t(N) / 2) * sizeof(float2), s),
+  HIP_TRY(scratch_alloc(reinterpret_cast<void **>(&scr), (nn + size_t(N) / 2) * sizeof(float2), s),
           "idg_wstack_to_image: scratch");
   float2 *tw = scr + nn;
   const float2 *g = reinterpret_cast<const float2 *>(grids_d);
@@ -1040,7 +1075,7 @@ int idg_image_to_wstack(const idg_cf32 *image_d, int32_t grid_size, double image
   const size_t nn = size_t(4) * N * N;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   float2 *scr = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&scr), (nn + size_t(N) / 2) * sizeof(float2), s),
+  HIP_TRY(scratch_alloc(reinterpret_cast<void **>(&scr), (nn + size_t(N) / 2) * sizeof(float2), s),
           "idg_image_to_wstack: scratch");
   float2 *tw = scr + nn;
   const float2 *img = reinterpret_cast<const float2 *>(image_d);
@@ -1133,7 +1168,7 @@ int idg_add_subgrids(idg_plan_t plan, const idg_cf32 *subgrids_d, int64_t first,
   const size_t b_part = size_t(ap.nslots) * 4 * idg::kAdderTile * idg::kAdderTile * sizeof(float2);
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   char *buf = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&buf), align(b_items) + align(b_comb) + align(b_con) + b_part + 256,
+  HIP_TRY(scratch_alloc(reinterpret_cast<void **>(&buf), align(b_items) + align(b_comb) + align(b_con) + b_part + 256,
                          s),
           "idg_add_subgrids: allocation");
   char *p_items = buf, *p_comb = p_items + align(b_items), *p_con = p_comb + align(b_comb);
@@ -1226,6 +1261,14 @@ int idg_profile_read(double *ms, int64_t *launches, int reset) {
     }
   }
   if (err != hipSuccess) return hip_fail(err, "idg_profile_read");
+  return IDG_OK;
+}
+
+int idg_trim_scratch(uint64_t keep_bytes) {
+  hipMemPool_t pool = nullptr;
+  HIP_TRY(scratch_pool(&pool), "idg_trim_scratch: pool");
+  HIP_TRY(hipDeviceSynchronize(), "idg_trim_scratch: synchronise");
+  HIP_TRY(hipMemPoolTrimTo(pool, size_t(keep_bytes)), "idg_trim_scratch");
   return IDG_OK;
 }
 

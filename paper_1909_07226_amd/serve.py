@@ -96,7 +96,8 @@ class JobFuture:
 class Server:
     """Continuous-batching scheduler: `slots` concurrent jobs (one HIP stream each), `mem_budget` bytes."""
 
-    def __init__(self, slots=4, mem_budget=None, device=None, poll_s=50e-6, large_slots=1, large_cost=4e9):
+    def __init__(self, slots=4, mem_budget=None, device=None, poll_s=50e-6, large_slots=1, large_cost=4e9,
+                 keep_results=True):
         import torch
         self.device = torch.device("cuda" if device is None else device)
         if mem_budget is None:
@@ -109,6 +110,7 @@ class Server:
         self.large_slots, self.large_cost = large_slots, large_cost
         self.large_in_use = 0
         self.poll_s = poll_s
+        self.keep_results = keep_results   # False: a finished job's output is dropped (latency measurements)
         self._queue = collections.deque()
         self._inflight = []
         self._cv = threading.Condition()
@@ -177,7 +179,7 @@ class Server:
             self.free_slots.append(slot)
             self.mem_in_use -= fut.job.mem_bytes
             self.large_in_use -= int(fut.job.cost >= self.large_cost)
-            fut._set(result=out)
+            fut._set(result=out if self.keep_results else None)
             self.completed.append(fut)
         return bool(done)
 
