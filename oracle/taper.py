@@ -132,6 +132,35 @@ def idg_window_matrix(L, max_shift, dps=None):
             ctx.__exit__(None, None, None)
 
 
+def side_lobe_matrix_at_shift(L, s):
+    """R(s) (L x L, float64): the side-lobe energy of the effective window at one position shift s (uv
+    pixels) is a^T R(s) a.  R(s) = Qbar o C(s) with C_kl(s) = cos(2 pi (k - l) s / L), the phasor product
+    z_k z_l^* of §4.2 without the average over shifts that gives Rbar; the mean of R(s) over |s| <= h is
+    idg_window_matrix(L, h).  Qbar is taken from idg_window_matrix at zero shift range (Sbar = 1)."""
+    q = idg_window_matrix(L, 0.0)
+    d = np.subtract.outer(np.arange(L), np.arange(L))
+    return q * np.cos(2 * np.pi * d * float(s) / L)
+
+
+def side_lobe_error_at_shift(a, s):
+    """The error of taper a for samples at position shift s from the subgrid centre (§4.3, the dependence
+    on position): sqrt(a^T R(s) a / a^T a)."""
+    a = np.asarray(a, np.float64)
+    return float(np.sqrt(max(a @ side_lobe_matrix_at_shift(a.size, s) @ a / (a @ a), 0.0)))
+
+
+def effective_window(a, s, x):
+    """The effective window f(x, s) of §4.2 at index-unit positions x (subgrid pixel k at x = k): the sinc
+    interpolation of the taper samples times the phase gradient of a sample shifted s uv pixels from the
+    subgrid centre, which cancels at the sample points:
+        f(x, s) = sum_k a_k sinc(x - k) exp(2 pi i (k - x) s / L)."""
+    a = np.asarray(a, np.float64)
+    L = a.size
+    k = np.arange(L)
+    x = np.atleast_1d(np.asarray(x, np.float64))
+    return (np.sinc(x[:, None] - k[None, :]) * np.exp(2j * np.pi * (k[None, :] - x[:, None]) * s / L)) @ a
+
+
 def idg_optimal_window(L, max_shift, dps=None):
     """(eps, a): eps = sqrt(smallest eigenvalue of Rbar), a its eigenvector (float64, a[L/2] = 1)."""
     R = idg_window_matrix(L, max_shift, dps)
