@@ -459,7 +459,14 @@ __device__ __forceinline__ void grid_finish(const KernelArgs &a, const DevSubgri
     const int pix = tid + r * NT;
     const int o = a.pieces ? piece_index<L>(pix / L, pix % L, ox, oy) : pix;
 #pragma unroll
-    for (int pol = 0; pol < 4; ++pol) out[pol * NPIX + o] = s_sg[SgLayout<L>::idx(pol, pix)];
+    for (int pol = 0; pol < 4; ++pol) {
+      // streamed past the caches: the adder reads the subgrids back only after the whole launch, by
+      // which time tens of GB have gone through; keeping them out leaves L2 and MALL to the Jones blocks
+      const float2 v = s_sg[SgLayout<L>::idx(pol, pix)];
+      double bits;
+      __builtin_memcpy(&bits, &v, 8);
+      __builtin_nontemporal_store(bits, reinterpret_cast<double *>(out + pol * NPIX + o));
+    }
   }
 }
 
@@ -1666,7 +1673,11 @@ __global__ void __launch_bounds__(256) adder_kernel(AdderArgs a) {
 #pragma unroll
           for (int k = 0; k < PER; ++k) {
             const int jb = ty * T + py + k * ROWS - d.y0;
-            if (jb >= 0 && jb < L) v[u][k] = sp[a.pieces ? piece_index<L>(jb, ia, ox, oy) : jb * L + ia];
+            if (jb >= 0 && jb < L) {  // read once: streamed
+              const double bits = __builtin_nontemporal_load(
+                  reinterpret_cast<const double *>(sp + (a.pieces ? piece_index<L>(jb, ia, ox, oy) : jb * L + ia)));
+              __builtin_memcpy(&v[u][k], &bits, 8);
+            }
           }
         }
       }
