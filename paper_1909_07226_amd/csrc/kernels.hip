@@ -1446,7 +1446,8 @@ __device__ __forceinline__ void degrid_one(const KernelArgs &a, int64_t p, SM &s
           a.grid_in[((int64_t(d.layer) * 4 + pol) * N + d.y0 + row) * N + d.x0 + col];
   }
   __syncthreads();
-  if constexpr (WIDE && L <= 32) lds_centred_dft_one_thread_per_line<L, NT, true>(sm.sg, sm.tw);
+  // one thread per line for the wide shape and the separable form (measured 3 % faster there, SKA-low-like)
+  if constexpr ((WIDE || PATH == kPathSep) && L <= 32) lds_centred_dft_one_thread_per_line<L, NT, true>(sm.sg, sm.tw);
   else lds_centred_dft<L, NT, true>(sm.sg, sm.tw);
 
   const float2 *j1 = a.aterms + int64_t(d.a1) * NPIX * 4;
