@@ -449,3 +449,14 @@ def test_trim_scratch_between_calls(gpu):
     idg.trim_scratch(1 << 20)
     idg.sync()
     assert torch.equal(g1, g2)
+
+
+def test_device_rates_are_plausible(gpu):
+    # the microkernels behind the benchmark's measured fractions: positive, below the published peaks, and the
+    # fp16 matrix cores far above the unpacked float32 multiply-adds
+    torch, idg = gpu
+    r = idg.device_rates()
+    assert 5.0 < r["fp32_fma_tflops"] <= 157.3 * 1.05
+    assert 10.0 < r["sincos_ginstr_per_s"] < 2000.0
+    assert 100.0 < r["fp16_mfma_tflops"] <= 2500.0 * 1.05
+    assert r["fp16_mfma_tflops"] > 8 * r["fp32_fma_tflops"]
