@@ -808,8 +808,9 @@ static hipError_t grid_launches(idg_plan_t plan, const DevPlan *dp, const double
       // separable form (matrix cores) over ord[0 .. n_sep), direct sum over the rest; two queue counters
       StageTimer tm(IDG_STAGE_GRIDDER, s);
       a.count = int32_t(b.n_sep);
+      // plain form with every subgrid of the batch separable: plan order (no list to load first)
       err = persistent ? idg::launch_gridder_mfma_persistent(L, a, ord, g.counter, nblocks_sep, s)
-                       : idg::launch_gridder_mfma(L, a, ord, s);
+                       : idg::launch_gridder_mfma(L, a, b.n_sep == b.count ? nullptr : ord, s);
       if (err == hipSuccess) {
         a.count = int32_t(b.count - b.n_sep);
         err = persistent ? idg::launch_gridder_persistent(L, a, ord + b.n_sep, g.counter + 1, nblocks, s)

@@ -80,7 +80,8 @@ bool supported_subgrid_size(int L);
 
 // Gridder, direct sum on the VALU: a.count subgrids, local indices order[0 .. count) (order NULL: 0 .. count).
 hipError_t launch_gridder(int L, const KernelArgs &a, const int32_t *order, hipStream_t s);
-// Gridder, separable form on the matrix cores (L = 32 only; subgrids with 0 <= order <= separable_max_order()).
+// Gridder, separable form on the matrix cores (L = 32 only; subgrids with 0 <= order <= separable_max_order()):
+// local indices order[0 .. count) (order NULL: 0 .. count).
 int separable_max_order();
 bool separable_supported(int L);
 hipError_t launch_gridder_mfma(int L, const KernelArgs &a, const int32_t *order, hipStream_t s);

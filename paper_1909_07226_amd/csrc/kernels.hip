@@ -869,7 +869,7 @@ __global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu
 gridder_mfma_kernel(KernelArgs a, const int32_t *order) {
   __shared__ GridderSmem<L> sm;
   if (threadIdx.x < L) sm.tw[threadIdx.x] = a.twiddle[threadIdx.x];
-  grid_one_mfma<L>(a, order[blockIdx.x], sm);
+  grid_one_mfma<L>(a, order ? order[blockIdx.x] : int(blockIdx.x), sm);
 }
 
 // Held to 2 waves per SIMD; the loop would otherwise take 1.  At 3 waves it measured slower (SKA-low-like
@@ -1594,7 +1594,7 @@ __global__ void __launch_bounds__(Cfg<L>::NT) __attribute__((amdgpu_waves_per_eu
 degridder_sep_kernel(KernelArgs a, const int32_t *order) {
   __shared__ DegridderSmem<L, true> sm;
   degrid_load_tables<L>(a, sm);
-  degrid_one<L, false, false, kPathSep>(a, order[blockIdx.x], sm);
+  degrid_one<L, false, false, kPathSep>(a, order ? int64_t(order[blockIdx.x]) : int64_t(blockIdx.x), sm);
 }
 
 template <int L>
@@ -1883,7 +1883,9 @@ hipError_t launch_degridder(int L, const KernelArgs &a, bool wide, const int32_t
   const int64_t n_small = a.count - n_sep - n_large;
   if (n_sep > 0) {
     if (L != 32 || a.phase_fp32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((degridder_sep_kernel<32>), dim3(unsigned(n_sep)), dim3(Cfg<32>::NT), 0, s, a, order);
+    // every subgrid in the separable form: plan order, one dependent load less per workgroup than the list
+    hipLaunchKernelGGL((degridder_sep_kernel<32>), dim3(unsigned(n_sep)), dim3(Cfg<32>::NT), 0, s, a,
+                       n_sep == a.count ? nullptr : order);
   }
   const int32_t *ol = order + n_sep, *os = order + n_sep + n_large;
   IDG_DISPATCH_L(L, {
