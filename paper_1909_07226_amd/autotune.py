@@ -101,6 +101,9 @@ def autotune(plan, uvw, freqs, vis, aterms, taper, grid, vis_out=None, reps=2, u
         _lib.degrid(plan, uvw, freqs, grid, aterms, taper, vis_out, stream)
 
     plan.set_tuning(sum_path="auto")
+    # the degridder shape selects among the direct-sum degridders only: with every subgrid in the separable
+    # form it changes nothing, and timing it would pick at random between equal times
+    shapes = DEGRID_SHAPES if plan.sum_paths()["direct"][0] > 0 else ("standard",)
     best_g = best_d = None
     for form, bpc in GRID_CANDIDATES:
         plan.set_tuning(grid_form=form, degrid_form=form, grid_blocks_per_cu=bpc, degrid_blocks_per_cu=bpc)
@@ -112,7 +115,7 @@ def autotune(plan, uvw, freqs, vis, aterms, taper, grid, vis_out=None, reps=2, u
         if best_g is None or tg < best_g[0]:
             best_g = (tg, form, bpc)
         tds = []
-        for shape in DEGRID_SHAPES:
+        for shape in shapes:
             plan.set_tuning(degrid_shape=shape)
             do_degrid()
             td = _stage_ms(do_degrid, "degridder", reps, stream)
