@@ -63,6 +63,7 @@ struct DevPlan {
   float2 *twiddle = nullptr;
   float2 *sep = nullptr;   // separable form: (x_q, a_q)
   float *cross = nullptr;  // separable form: c_ij
+  int cross_exp = 0;       // max |c_ij| <= 2^cross_exp
   int32_t *grid_order = nullptr, *degrid_order = nullptr, *contrib = nullptr;
   idg::AdderItem *items = nullptr;
   idg::CombineItem *combine = nullptr;
@@ -372,6 +373,7 @@ int device_plan(idg_plan_t plan, DevPlan **out) {
   std::vector<float2> sep;
   std::vector<float> cross;
   const double cmax = separable_tables(L, p.image_size, sep, cross);
+  if (cmax > 0.0) (void)std::frexp(cmax, &dp->cross_exp);  // cmax < 2^cross_exp
   // separable form: the expansion order and the power-of-two bound of |w - w_0p| per subgrid
   if (separable_on(plan))
     for (size_t i = 0; i < subs.size(); ++i) {
@@ -663,6 +665,7 @@ static void fill_kernel_args(const idg_plan_s *plan, const DevPlan *dp, idg::Ker
   a.twiddle = dp->twiddle;
   a.sep = dp->sep;
   a.cross = dp->cross;
+  a.cross_exp = dp->cross_exp;
   a.nr_timesteps = p.nr_timesteps;
   a.nr_channels = p.nr_channels;
   a.grid_size = p.grid_size;

@@ -36,6 +36,7 @@ struct KernelArgs {
   const float2 *twiddle;       // [L] exp(-2 pi i k / L)
   const float2 *sep;           // [L] (x_q, sqrt(1 - x_q^2) - 1), x_q = (q - L/2) S / L (separable form)
   const float *cross;          // [L*L] n'_ij - a_i - a_j (separable form)
+  int32_t cross_exp;           // separable form: max |c_ij| <= 2^cross_exp
   const float2 *grid_in;       // degridder: [4][N][N]
   float2 *subgrids_out;        // gridder: [count][4][L*L]
   int64_t first;               // first plan subgrid of this launch

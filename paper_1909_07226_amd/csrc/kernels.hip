@@ -1276,6 +1276,7 @@ __device__ __forceinline__ void degrid_sep(const KernelArgs &a, const DevSubgrid
   int bexp = -126;
   if (sm.ybits) (void)frexpf(__uint_as_float(sm.ybits), &bexp);  // largest < 2^bexp
   const float binv = ldexpf(1.0f, -bexp);
+  const float cinv = ldexpf(1.0f, -a.cross_exp);
   // A operands of this wave's polarisation: row j = col, columns i = 16 q + 8 hw + s (s = 0..7)
   half8 arh[2], arl[2], aih[2], ail[2], acr[2], aci[2];
 #pragma unroll
@@ -1294,7 +1295,8 @@ __device__ __forceinline__ void degrid_sep(const KernelArgs &a, const DevSubgrid
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
         const int i = 16 * q + 8 * hw + 2 * s2;
-        const float c0 = a.cross[col * L + i], c1 = a.cross[col * L + i + 1];
+        // c_ij scaled by 2^-cross_exp to at most 1: unscaled (|c| ~ 1e-7) its products would underflow fp16
+        const float c0 = a.cross[col * L + i] * cinv, c1 = a.cross[col * L + i + 1] * cinv;
         const auto hr = __builtin_amdgcn_cvt_pkrtz(c0 * xr[2 * s2], c1 * xr[2 * s2 + 1]);
         const auto hi = __builtin_amdgcn_cvt_pkrtz(c0 * xi[2 * s2], c1 * xi[2 * s2 + 1]);
         acr[q][2 * s2] = hr[0];
@@ -1381,7 +1383,7 @@ __device__ __forceinline__ void degrid_sep(const KernelArgs &a, const DevSubgrid
       }
       // Y_k = sum_j conj(V_k(j)) (T_0 - 2 pi i dw T_1) over this lane's rows j, then the other half-wave's
       float yr = 0.0f, yi = 0.0f;
-      const float w2 = twopi * dw;
+      const float w2 = twopi * ldexpf(dw, a.cross_exp);  // T_1 carries c 2^-cross_exp
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         // rows j = 8 g + 4 hw + (0 .. 3): accumulator elements e = 4 g .. 4 g + 3

@@ -419,7 +419,7 @@ def test_separable_degridder_matches_oracle(gpu, name, form):
     for p in range(oplan.nr_subgrids):
         tc = oplan.subgrid_samples(p)
         planned[oplan.subgrids[p, F["bl"]], tc[:, 0], tc[:, 1]] = True
-    out = {}
+    out, err = {}, {}
     for path in ("auto", "direct"):
         plan = idg.Plan.from_workload(wl)
         plan.set_tuning(form=form, sum_path=path)
@@ -428,10 +428,14 @@ def test_separable_degridder_matches_oracle(gpu, name, form):
         idg.sync()
         got = v.cpu().numpy()
         out[path] = got
-        say(f"    {path}: vis rms rel {rms_rel(got[planned], ref[planned]):.2e}")
-        assert rms_rel(got[planned], ref[planned]) < VIS_RMS_TOL, path
+        err[path] = rms_rel(got[planned], ref[planned])
+        say(f"    {path}: vis rms rel {err[path]:.2e}")
+        assert err[path] < VIS_RMS_TOL, path
         assert np.all(got[~planned] == 0)
     assert rms_rel(out["auto"][planned], out["direct"][planned]) < VIS_RMS_TOL
+    # the separable form is as accurate as the direct sum: its first-order term must not lose precision (the
+    # cross term c ~ 1e-7 underflowed fp16 before it was scaled by 2^-cross_exp, which cost 2-6x here)
+    assert err["auto"] < 1.5 * err["direct"] + 2e-7, err
 
 
 def test_trim_scratch_between_calls(gpu):
