@@ -55,7 +55,7 @@ import numpy as np
 FLOP_PER_VIS_PIX = 34
 FLOP_PER_PIX_ATERM = 136
 # MI355X published FP32 vector peak: 256 CUs x 256 flop per CU-cycle x 2.4 GHz, which counts packed FMAs
-# (2 per lane per instruction); this build issues unpacked FMAs only, which reach half of it
+# (2 per lane per instruction); the library's kernels issue unpacked FMAs only, which reach half of it
 FP32_PEAK_TFLOPS = 157.3
 # MI355X dense fp16 matrix-core peak (no structured sparsity)
 FP16_MFMA_PEAK_TFLOPS = 2500.0
